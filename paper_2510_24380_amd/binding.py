@@ -1,0 +1,315 @@
+"""ctypes binding of libapex.so (include/apex.h). Argument marshalling only:
+every step of the search runs in the library's HIP kernels. torch provides the
+device memory (engine and query workspaces, tables, weights) and the stream.
+
+Raises if the library is not built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libapex.so")
+
+APEX_OK = 0
+STATUS = {0: "APEX_OK", -1: "APEX_E_INVALID", -2: "APEX_E_NOMEM", -3: "APEX_E_DEVICE",
+          -4: "APEX_E_UNSUPPORTED", -5: "APEX_E_PENDING", -6: "APEX_E_CANCELLED"}
+ACT = {"none": 0, "relu": 1, "silu": 2}
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+
+P = ctypes.c_void_p
+U32 = ctypes.c_uint32
+U64 = ctypes.c_uint64
+
+
+class ApexError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class LibraryDesc(ctypes.Structure):
+    _fields_ = [("n_reactions", U32), ("n_slots", P), ("slot_sizes", P), ("d", U32), ("tables", P)]
+
+
+class DecoderDesc(ctypes.Structure):
+    _fields_ = [("n_layers", U32), ("dims", P), ("act", U32), ("W", P), ("b", P)]
+
+
+class ConstraintC(ctypes.Structure):
+    _fields_ = [("head", U32), ("lo", ctypes.c_float), ("hi", ctypes.c_float)]
+
+
+class QueryC(ctypes.Structure):
+    _fields_ = [("objective_w", P), ("n_constraints", U32), ("constraints", P), ("k", U64),
+                ("precision", U32), ("pool_factor", U32), ("n_subset", U32), ("subset", P)]
+
+
+class ResultC(ctypes.Structure):
+    _fields_ = [("capacity", U64), ("ids", P), ("objective", P), ("heads", P), ("reaction", P),
+                ("synthon", P), ("n_found", U64), ("n_scored", U64), ("n_candidates", U64),
+                ("n_reruns", U32)]
+
+
+class ServerConfigC(ctypes.Structure):
+    _fields_ = [("pool", P), ("pool_bytes", ctypes.c_size_t), ("max_active", U32), ("stream", P),
+                ("chunk_compounds", U64)]
+
+
+class ServerStatsC(ctypes.Structure):
+    _fields_ = [("submitted", U64), ("completed", U64), ("cancelled", U64), ("failed", U64),
+                ("active", U64), ("waiting", U64), ("p50_latency_ms", ctypes.c_double),
+                ("p99_latency_ms", ctypes.c_double), ("max_latency_ms", ctypes.c_double),
+                ("compounds_per_s", ctypes.c_double), ("compounds_scored", U64)]
+
+
+_lib = None
+
+_SIGS = {
+    "apex_library_create": [P, P],
+    "apex_library_destroy": [P],
+    "apex_library_num_compounds": [P, P],
+    "apex_decode_ids": [P, P, ctypes.c_size_t, P, P],
+    "apex_decoder_create": [P, P],
+    "apex_decoder_destroy": [P],
+    "apex_engine_workspace_size": [P, P, U32, P],
+    "apex_engine_create": [P, P, U32, P, ctypes.c_size_t, P, P],
+    "apex_engine_destroy": [P],
+    "apex_query_workspace_size": [P, P, P],
+    "apex_search": [P, P, P, ctypes.c_size_t, P, P],
+    "apex_batch_workspace_size": [P, P, U32, P],
+    "apex_search_batch": [P, P, U32, P, ctypes.c_size_t, P, P],
+    "apex_engine_profile": [P, ctypes.c_int, P, P, P],
+    "apex_server_create": [P, P, P],
+    "apex_server_submit": [P, P, P],
+    "apex_server_poll": [P, U64, P, ctypes.c_int],
+    "apex_server_cancel": [P, U64],
+    "apex_server_stats_get": [P, P],
+    "apex_server_destroy": [P],
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is missing: build it with paper_2510_24380_amd.build.build()")
+        L = ctypes.CDLL(SO_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.apex_status_string.argtypes = [ctypes.c_int]
+        L.apex_status_string.restype = ctypes.c_char_p
+        L.apex_last_error.argtypes = []
+        L.apex_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != APEX_OK:
+        raise ApexError(status, lib().apex_last_error().decode())
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return int(t.data_ptr())
+
+
+class Library:
+    """Reactions, slot sizes and the FP32 synthon table (device, rows in
+    (reaction, slot, synthon) order). Keeps the table tensor alive."""
+
+    def __init__(self, n_slots: Sequence[int], slot_sizes: Sequence[int], tables: torch.Tensor):
+        if tables.dtype != torch.float32 or tables.dim() != 2 or not tables.is_contiguous():
+            raise ValueError("tables must be a contiguous 2-D float32 tensor")
+        self.tables = tables
+        self._ns = np.ascontiguousarray(n_slots, dtype=np.uint32)
+        self._ss = np.ascontiguousarray(slot_sizes, dtype=np.uint32)
+        desc = LibraryDesc(len(self._ns), self._ns.ctypes.data, self._ss.ctypes.data, tables.shape[1],
+                           _dev_ptr(tables))
+        h = P()
+        _check(lib().apex_library_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.n_reactions = len(self._ns)
+
+    @property
+    def num_compounds(self) -> int:
+        n = U64()
+        _check(lib().apex_library_num_compounds(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    def decode(self, ids):
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        r = np.zeros(max(ids.size, 1), np.uint32)
+        s = np.zeros((max(ids.size, 1), 3), np.uint32)
+        _check(lib().apex_decode_ids(self.handle, ids.ctypes.data, ids.size, r.ctypes.data, s.ctypes.data))
+        return r[:ids.size], s[:ids.size]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.apex_library_destroy(self.handle)
+            self.handle = None
+
+
+class Decoder:
+    """Decoder weights (device FP32): W[l] is dims[l+1] x dims[l]."""
+
+    def __init__(self, dims: Sequence[int], act: str, W: Sequence[torch.Tensor], b: Sequence[torch.Tensor]):
+        self.W = [w.contiguous() for w in W]
+        self.b = [x.contiguous() for x in b]
+        self._dims = np.ascontiguousarray(dims, dtype=np.uint32)
+        self._wp = (ctypes.c_void_p * len(self.W))(*[_dev_ptr(w) for w in self.W])
+        self._bp = (ctypes.c_void_p * len(self.b))(*[_dev_ptr(x) for x in self.b])
+        desc = DecoderDesc(len(self.W), self._dims.ctypes.data, ACT[act] if isinstance(act, str) else int(act),
+                           ctypes.cast(self._wp, P), ctypes.cast(self._bp, P))
+        h = P()
+        _check(lib().apex_decoder_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.dims = [int(x) for x in dims]
+
+    @property
+    def n_heads(self) -> int:
+        return self.dims[-1]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.apex_decoder_destroy(self.handle)
+            self.handle = None
+
+
+@dataclasses.dataclass
+class SearchResult:
+    ids: np.ndarray
+    objective: np.ndarray
+    heads: np.ndarray
+    reaction: np.ndarray
+    synthon: np.ndarray
+    n_scored: int
+    n_candidates: int
+    n_reruns: int
+
+
+class _QueryMarshal:
+    """Keeps the ctypes arrays of one query alive."""
+
+    def __init__(self, q, n_heads: int, precision: str, pool_factor: int):
+        w = np.zeros(n_heads, np.float32)
+        w[:len(q.w)] = np.asarray(q.w, np.float32)[:n_heads]
+        self.w = w
+        cons = list(q.constraints)
+        self.cons = (ConstraintC * max(len(cons), 1))()
+        for i, c in enumerate(cons):
+            lo = -math.inf if c.lo is None else float(c.lo)
+            hi = math.inf if c.hi is None else float(c.hi)
+            self.cons[i] = ConstraintC(int(c.head), lo, hi)
+        subset = getattr(q, "reactions", None)
+        self.subset = np.ascontiguousarray(list(subset) if subset is not None else [0], dtype=np.uint32)
+        self.c = QueryC(self.w.ctypes.data, len(cons), ctypes.cast(self.cons, P), int(q.k), PREC[precision],
+                        int(pool_factor), len(subset) if subset is not None else 0,
+                        self.subset.ctypes.data if subset is not None else None)
+
+
+class _ResultMarshal:
+    def __init__(self, k: int, n_heads: int):
+        self.ids = np.zeros(k, np.uint64)
+        self.obj = np.zeros(k, np.float32)
+        self.heads = np.zeros((k, n_heads), np.float32)
+        self.reaction = np.zeros(k, np.uint32)
+        self.synthon = np.zeros((k, 3), np.uint32)
+        self.c = ResultC(k, self.ids.ctypes.data, self.obj.ctypes.data, self.heads.ctypes.data,
+                         self.reaction.ctypes.data, self.synthon.ctypes.data, 0, 0, 0, 0)
+
+    def result(self) -> SearchResult:
+        n = int(self.c.n_found)
+        return SearchResult(self.ids[:n].copy(), self.obj[:n].copy(), self.heads[:n].copy(),
+                            self.reaction[:n].copy(), self.synthon[:n].copy(), int(self.c.n_scored),
+                            int(self.c.n_candidates), int(self.c.n_reruns))
+
+
+class Engine:
+    """Resident hoisted tables and decoder layouts for one (library, decoder)."""
+
+    def __init__(self, library: Library, decoder: Decoder, precisions=("fp32", "bf16", "fp8"),
+                 stream: Optional[torch.cuda.Stream] = None):
+        mask = 0
+        for p in precisions:
+            mask |= 1 << PREC[p]
+        n = ctypes.c_size_t()
+        _check(lib().apex_engine_workspace_size(library.handle, decoder.handle, mask, ctypes.byref(n)))
+        self.workspace = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device="cuda")
+        h = P()
+        _check(lib().apex_engine_create(library.handle, decoder.handle, mask, self.workspace.data_ptr(),
+                                        self.workspace.numel(), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.library = library
+        self.decoder = decoder
+        self.n_heads = decoder.n_heads
+        self._qws = None
+
+    def _workspace(self, nbytes: int) -> torch.Tensor:
+        if self._qws is None or self._qws.numel() < nbytes:
+            self._qws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+        return self._qws
+
+    def query_workspace_size(self, q, precision="fp32", pool_factor=0) -> int:
+        m = _QueryMarshal(q, self.n_heads, precision, pool_factor)
+        n = ctypes.c_size_t()
+        _check(lib().apex_query_workspace_size(self.handle, ctypes.byref(m.c), ctypes.byref(n)))
+        return int(n.value)
+
+    def search(self, q, precision: str = "fp32", pool_factor: int = 0,
+               stream: Optional[torch.cuda.Stream] = None) -> SearchResult:
+        return self.search_batch([q], precision, pool_factor, stream)[0]
+
+    def search_batch(self, qs, precision: str = "fp32", pool_factor: int = 0,
+                     stream: Optional[torch.cuda.Stream] = None) -> List[SearchResult]:
+        ms = [_QueryMarshal(q, self.n_heads, precision, pool_factor) for q in qs]
+        arr = (QueryC * len(ms))(*[m.c for m in ms])
+        n = ctypes.c_size_t()
+        _check(lib().apex_batch_workspace_size(self.handle, arr, len(ms), ctypes.byref(n)))
+        ws = self._workspace(int(n.value))
+        rs = [_ResultMarshal(int(q.k), self.n_heads) for q in qs]
+        rarr = (ResultC * len(rs))(*[r.c for r in rs])
+        if len(ms) == 1:
+            st = lib().apex_search(self.handle, arr, ws.data_ptr(), ws.numel(), _stream_ptr(stream), rarr)
+        else:
+            st = lib().apex_search_batch(self.handle, arr, len(ms), ws.data_ptr(), ws.numel(),
+                                         _stream_ptr(stream), rarr)
+        _check(st)
+        out = []
+        for r, rc in zip(rs, rarr):
+            r.c = rc
+            out.append(r.result())
+        return out
+
+    def profile(self, enable: bool):
+        """Returns (ms, launches, compounds) timed since the last call, then
+        switches timing of the fused kernel on or off."""
+        ms = ctypes.c_double()
+        nl = U64()
+        nc = U64()
+        _check(lib().apex_engine_profile(self.handle, int(enable), ctypes.byref(ms), ctypes.byref(nl),
+                                         ctypes.byref(nc)))
+        return float(ms.value), int(nl.value), int(nc.value)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.apex_engine_destroy(self.handle)
+            self.handle = None

@@ -1,0 +1,106 @@
+// Internal types shared by the HIP kernels and the host engine (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/apex.h"
+
+namespace apex {
+
+constexpr int kWaves = 8;              // waves per workgroup of the fused kernel
+constexpr int kThreads = kWaves * 64;  // 512
+constexpr int kRowPad = 4;             // LDS row padding (floats) for staged synthon rows
+constexpr int kHeadsPad = 16;          // heads are padded to one 16-wide MFMA tile
+constexpr uint32_t kSelectThreads = 1024;
+
+// Tile geometry per precision: every wave holds R blocks of 16 compounds. A block
+// is one "A" row (slot 0, or slots 0 and 1 for three-slot reactions) against 16
+// consecutive "B" rows (the last slot).
+template <int PREC> struct TileShape;
+template <> struct TileShape<APEX_PREC_FP32> { static constexpr int R = 1, TA = 8, NB = 1; };
+template <> struct TileShape<APEX_PREC_BF16> { static constexpr int R = 2, TA = 16, NB = 1; };
+template <> struct TileShape<APEX_PREC_FP8> { static constexpr int R = 4, TA = 16, NB = 2; };
+
+inline int tile_ta(int prec) { return prec == APEX_PREC_FP32 ? 8 : 16; }
+inline int tile_tb(int prec) { return prec == APEX_PREC_FP8 ? 32 : 16; }
+
+// One reaction of the library as the kernels see it: every compound is a pair
+// (a, b) with a over the first slot(s) and b over the last slot.
+struct ReactDev {
+  uint64_t id_off;  // id of the reaction's first compound
+  uint32_t row0;    // table row of synthon 0 of slot 0
+  uint32_t row1;    // table row of synthon 0 of slot 1 (three-slot reactions)
+  uint32_t rowB;    // table row of synthon 0 of the last slot
+  uint32_t n1;      // synthons in slot 1 (three-slot: a = i0 * n1 + i1)
+  uint32_t nA;      // n0, or n0 * n1 for three slots
+  uint32_t nB;      // synthons in the last slot
+  uint32_t three;   // 1 for a three-slot reaction
+  uint32_t pad;
+};
+
+// A reaction selected for a pass, with its place in the pass's tile sequence.
+struct SelDev {
+  uint64_t tile_start;      // first tile index of this reaction in the pass
+  uint64_t compound_start;  // first compound (in selection order) of this reaction
+  uint32_t t;               // reaction index
+  uint32_t tiles_b;         // tiles along b
+};
+
+// Per-precision decoder state resident in the engine workspace.
+struct PrecDev {
+  const void* w2;      // GEMM2 fragments [H2/16][H1/KS][64][E] (n_layers == 3)
+  const void* wo;      // final-layer fragments
+  const float* b2;     // GEMM2 accumulator initial values [H2]
+  const float* bo;     // final bias [16]
+  const float* scal;   // [0] GEMM2 scale S2, [1] final scale So, [2] X conversion scale
+  const float* delta;  // [16] per-head relaxation used while enumerating in low precision
+};
+
+// Running state of one query's candidate buffer.
+struct QState {
+  float tau_o;        // threshold key: pass iff o > tau_o or (o == tau_o and id <= tau_id)
+  uint32_t pad0;
+  uint64_t tau_id;
+  uint32_t count;     // entries appended (may exceed cap)
+  uint32_t chunk_base;// count when the current chunk began
+  uint32_t overflow;  // chunks re-run so far are flagged in the rerun list
+  uint32_t pad1;
+  uint64_t appended;  // total appends over the search
+};
+
+// Query parameters for the fused kernel and the scoring kernels.
+struct QueryDev {
+  float w[kHeadsPad];
+  float lo[kHeadsPad];   // per-head lower bound (intersection of the query's bounds)
+  float hi[kHeadsPad];
+  QState* st;
+  float* cand_o;         // candidate buffer [cap]
+  uint64_t* cand_id;
+  float* tmp_o;          // compaction scratch [K]
+  uint64_t* tmp_id;
+  uint32_t* rerun;       // per-chunk overflow flags
+  const uint32_t* subset_bits;  // [ceil(T/32)] or null (all reactions)
+  uint32_t cap;
+  uint32_t K;            // entries kept (k, or the low-precision pool size)
+  uint32_t hwm;          // compaction trigger
+  uint32_t active;       // 0: skip this query in a pass
+};
+
+struct EnumArgs {
+  const float* P;          // hoisted tables [rows][H1] FP32
+  const ReactDev* react;
+  const SelDev* sel;
+  uint32_t n_sel;
+  uint64_t tile_begin, tile_end;  // tiles of this launch
+  PrecDev pd;
+  uint32_t H2;             // second hidden width (n_layers == 3)
+  uint32_t n_queries;
+  const QueryDev* queries;
+  // gather mode
+  const uint64_t* ids;     // compound ids
+  uint32_t n_ids;
+  uint64_t n_reactions;
+  float* heads_out;        // [n_ids][16]
+};
+
+}  // namespace apex

@@ -1,0 +1,47 @@
+// Selection and launch of the fused enumeration kernel instantiations.
+#include "enum_kernel.h"
+#include "launch.h"
+
+namespace apex {
+
+const void* enum_kernel_fp32(int h1, int nl, int act, bool gather);
+const void* enum_kernel_bf16(int h1, int nl, int act, bool gather);
+const void* enum_kernel_fp8(int h1, int nl, int act, bool gather);
+
+static const void* enum_kernel(int prec, int h1, int nl, int act, bool gather) {
+  if (prec == APEX_PREC_FP32) return enum_kernel_fp32(h1, nl, act, gather);
+  if (prec == APEX_PREC_BF16) return enum_kernel_bf16(h1, nl, act, gather);
+  if (prec == APEX_PREC_FP8) return enum_kernel_fp8(h1, nl, act, gather);
+  return nullptr;
+}
+
+int enum_rows_per_block_wave(int prec) {
+  return prec == APEX_PREC_FP32 ? TileShape<APEX_PREC_FP32>::R
+                                : (prec == APEX_PREC_BF16 ? TileShape<APEX_PREC_BF16>::R : TileShape<APEX_PREC_FP8>::R);
+}
+
+hipError_t enum_prepare(int prec, int h1, int nl, int act, bool gather, uint32_t h2, int* max_wg_per_cu) {
+  const void* k = enum_kernel(prec, h1, nl, act, gather);
+  if (!k) return hipErrorInvalidValue;
+  const int lds = enum_lds_bytes(prec, h1, nl, (int)h2, gather);
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  if (max_wg_per_cu) {
+    int n = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kThreads, lds);
+    if (e != hipSuccess) return e;
+    *max_wg_per_cu = n;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_enum(int prec, int h1, int nl, int act, bool gather, const EnumArgs& a, uint32_t grid,
+                       hipStream_t s) {
+  const void* k = enum_kernel(prec, h1, nl, act, gather);
+  if (!k) return hipErrorInvalidValue;
+  const int lds = enum_lds_bytes(prec, h1, nl, (int)a.H2, gather);
+  void* args[] = {const_cast<EnumArgs*>(&a)};
+  return hipLaunchKernel(k, dim3(grid), dim3(kThreads), args, (size_t)lds, s);
+}
+
+}  // namespace apex

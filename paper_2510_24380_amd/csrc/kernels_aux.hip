@@ -1,0 +1,589 @@
+// Engine-build kernels (hoist, scales, weight layouts) and the selection kernels
+// of the search: candidate scoring, radix select with compaction, rank sort,
+// id sampling and id decoding.
+#include "enum_kernel.h"
+#include "launch.h"
+
+namespace apex {
+
+// ---------------------------------------------------------------------------
+// Hoist (Section 4.3, eq. "apex"): the first decoder layer is linear in the
+// compound embedding, so it distributes over the slot sum and is applied once
+// per synthon row: P[r] = c * (W1 u_r + [r in slot 0] b1). Tiled FP32 GEMM,
+// 64 x 64 outputs per workgroup, k in ascending order for every output.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hoist(const float* __restrict__ U, uint32_t d, uint64_t rows,
+                                               const float* __restrict__ W1, const float* __restrict__ b1,
+                                               uint32_t h1, const uint8_t* __restrict__ is_slot0, float c,
+                                               float* __restrict__ P) {
+  __shared__ float sU[16][65];
+  __shared__ float sW[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const uint64_t r0 = (uint64_t)blockIdx.x * 64;
+  const uint32_t n0 = blockIdx.y * 64;
+  float acc[4][4] = {};
+  for (uint32_t k0 = 0; k0 < d; k0 += 16) {
+    for (int i = threadIdx.x; i < 16 * 64; i += 256) {
+      const int kk = i & 15, rr = i >> 4;
+      const uint64_t r = r0 + rr;
+      const uint32_t k = k0 + kk;
+      sU[kk][rr] = (r < rows && k < d) ? U[r * d + k] : 0.0f;
+      const uint32_t n = n0 + rr;
+      sW[kk][rr] = (n < h1 && k < d) ? W1[(uint64_t)n * d + k] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sU[kk][ty * 4 + i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b[i] = sW[kk][tx * 4 + i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = fmaf(a[i], b[q], acc[i][q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint64_t r = r0 + ty * 4 + i;
+    if (r >= rows) continue;
+    const bool s0 = is_slot0[r] != 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t n = n0 + tx * 4 + q;
+      if (n < h1) P[r * h1 + n] = c * (acc[i][q] + (s0 ? b1[n] : 0.0f));
+    }
+  }
+}
+
+// Per slot and column: extremes of P over the slot's rows.
+__global__ void k_colext(const float* __restrict__ P, uint32_t h1, const uint64_t* __restrict__ slot_row0,
+                         const uint32_t* __restrict__ slot_size, float* __restrict__ cmax, float* __restrict__ cmin) {
+  const uint32_t slot = blockIdx.x;
+  const uint32_t n = blockIdx.y * blockDim.x + threadIdx.x;
+  if (n >= h1) return;
+  float mx = -INFINITY, mn = INFINITY;
+  const uint64_t r0 = slot_row0[slot];
+  for (uint32_t i = 0; i < slot_size[slot]; ++i) {
+    const float x = P[(r0 + i) * h1 + n];
+    mx = fmaxf(mx, x);
+    mn = fminf(mn, x);
+  }
+  cmax[(uint64_t)slot * h1 + n] = mx;
+  cmin[(uint64_t)slot * h1 + n] = mn;
+}
+
+__device__ inline void atomic_max_nonneg(float* addr, float v) {
+  atomicMax(reinterpret_cast<unsigned int*>(addr), __float_as_uint(v));
+}
+
+// Largest |activation| any compound can produce in the first hidden layer, from
+// the per-slot column extremes: h ranges over [sum of minima, sum of maxima].
+__global__ void k_actmax(const float* __restrict__ cmax, const float* __restrict__ cmin, uint32_t h1,
+                         const uint32_t* __restrict__ react_slot0, const uint32_t* __restrict__ react_nslots,
+                         uint32_t n_react, int act, float c, float* __restrict__ out) {
+  const uint32_t t = blockIdx.x;
+  const uint32_t n = blockIdx.y * blockDim.x + threadIdx.x;
+  if (t >= n_react || n >= h1) return;
+  float hi = 0.0f, lo = 0.0f;
+  for (uint32_t s = 0; s < react_nslots[t]; ++s) {
+    hi += cmax[(uint64_t)(react_slot0[t] + s) * h1 + n];
+    lo += cmin[(uint64_t)(react_slot0[t] + s) * h1 + n];
+  }
+  float m;
+  if (act == APEX_ACT_SILU) {
+    // tables carry c < 0; x = h / c ranges over [hi / c, lo / c]
+    const float x1 = hi / c, x2 = lo / c;
+    const float s1 = fabsf(x1 / (1.0f + expf(-x1))), s2 = fabsf(x2 / (1.0f + expf(-x2)));
+    m = fabsf(c) * fmaxf(fmaxf(s1, s2), 0.2785f);
+  } else if (act == APEX_ACT_RELU) {
+    m = fmaxf(hi, 0.0f);
+  } else {
+    m = fmaxf(fabsf(hi), fabsf(lo));
+  }
+  atomic_max_nonneg(out, m);
+}
+
+__global__ void k_absmax(const float* __restrict__ x, uint64_t n, float* __restrict__ out) {
+  float m = 0.0f;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(x[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
+}
+
+// Scales of one precision. amax: [0] activation range, [1] |W2|, [2] |Wo|.
+// scal: [0] S2, [1] So, [2] X conversion scale, [3] 1/s_w2, [4] 1/s_wo.
+__global__ void k_scales(const float* __restrict__ amax, int prec, int nl, float* __restrict__ scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float S2 = 1.0f, So = 1.0f, xs = 1.0f, iw2 = 1.0f, iwo = 1.0f;
+  if (prec == APEX_PREC_FP8) {
+    const float ax = amax[0] > 0.0f ? amax[0] : 1.0f;
+    xs = exp2f(ceilf(log2f(ax / 448.0f)));
+    const float sw2 = amax[1] > 0.0f ? amax[1] / 448.0f : 1.0f;
+    const float swo = amax[2] > 0.0f ? amax[2] / 448.0f : 1.0f;
+    iw2 = 1.0f / sw2;
+    iwo = 1.0f / swo;
+    if (nl == 2) S2 = sw2 * xs;
+    else So = swo * xs;
+  }
+  scal[0] = S2;
+  scal[1] = So;
+  scal[2] = xs;
+  scal[3] = iw2;
+  scal[4] = iwo;
+}
+
+template <int PREC> __device__ inline void store_elem(void* base, uint64_t i, float v);
+template <> __device__ inline void store_elem<APEX_PREC_FP32>(void* base, uint64_t i, float v) {
+  reinterpret_cast<float*>(base)[i] = v;
+}
+template <> __device__ inline void store_elem<APEX_PREC_BF16>(void* base, uint64_t i, float v) {
+  reinterpret_cast<__bf16*>(base)[i] = (__bf16)v;
+}
+template <> __device__ inline void store_elem<APEX_PREC_FP8>(void* base, uint64_t i, float v) {
+  v = fminf(fmaxf(v, -448.0f), 448.0f);
+  s16x2 p = {0, 0};
+  p = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(p, v, 0.0f, 1.0f, false);
+  reinterpret_cast<uint8_t*>(base)[i] = (uint8_t)(__builtin_bit_cast(uint32_t, p) & 0xffu);
+}
+
+// Operand fragments of a weight matrix W [n_out x n_in] (row-major) for a layer
+// whose input activations are in the kernel's X order: fragment (c, s, lane, e)
+// holds W[16 c + lane % 16][g n_in/4 + s E + e] * mul, g = lane / 16.
+template <int PREC>
+__global__ void k_frag_x(const float* __restrict__ W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
+                         const float* __restrict__ mul_dev, float mul, void* __restrict__ out) {
+  constexpr int E = MfmaT<PREC>::E;
+  const uint32_t ns = n_in / MfmaT<PREC>::KS;
+  const uint64_t total = (uint64_t)n_chunks * ns * 64 * E;
+  const float m = mul * (mul_dev ? *mul_dev : 1.0f);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = i % E;
+    const uint32_t lane = (i / E) % 64;
+    const uint32_t s = (i / ((uint64_t)E * 64)) % ns;
+    const uint32_t c = (uint32_t)(i / ((uint64_t)E * 64 * ns));
+    const uint32_t row = 16 * c + lane % 16;
+    const uint32_t k = (lane / 16) * (n_in / 4) + s * E + e;
+    const float v = row < n_out ? W[(uint64_t)row * n_in + k] * m : 0.0f;
+    store_elem<PREC>(out, i, v);
+  }
+}
+
+// Final-layer fragments when its input is the GEMM output in the 16x16 D layout
+// (lane group g holds neurons 4 g + v of every 16-neuron chunk).
+// fp32 (16x16x4): index (c, v, lane) -> Wo[lane % 16][16 c + 4 g + v].
+// bf16 (16x16x32, chunks in pairs p): (p, lane, e) -> Wo[lane % 16][32 p + 4 g + e]
+// for e < 4 and Wo[lane % 16][32 p + 16 + 4 g + e - 4] for e >= 4.
+__global__ void k_frag_out_d(const float* __restrict__ Wo, uint32_t H, uint32_t h2, int bf16, float mul,
+                             void* __restrict__ out) {
+  const uint32_t total = 16 * h2;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    uint32_t head, neuron;
+    if (!bf16) {
+      const uint32_t lane = i % 64, v = (i / 64) % 4, c = i / 256;
+      head = lane % 16;
+      neuron = 16 * c + 4 * (lane / 16) + v;
+    } else {
+      const uint32_t e = i % 8, lane = (i / 8) % 64, p = i / 512;
+      head = lane % 16;
+      neuron = 32 * p + (e < 4 ? 4 * (lane / 16) + e : 16 + 4 * (lane / 16) + (e - 4));
+    }
+    const float v = head < H ? Wo[(uint64_t)head * h2 + neuron] * mul : 0.0f;
+    if (!bf16) reinterpret_cast<float*>(out)[i] = v;
+    else reinterpret_cast<__bf16*>(out)[i] = (__bf16)v;
+  }
+}
+
+// GEMM accumulator start values c * b2 / S2, and the padded final bias.
+__global__ void k_bias(const float* __restrict__ b2, uint32_t h2, float c, const float* __restrict__ scal,
+                       const float* __restrict__ bo, uint32_t H, float* __restrict__ b2_out,
+                       float* __restrict__ bo_out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b2 && i < h2) b2_out[i] = c * b2[i] / scal[0];
+  if (i < kHeadsPad) bo_out[i] = i < H ? bo[i] : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Scoring of gathered heads (objective in the fused kernel's order) and append.
+// ---------------------------------------------------------------------------
+__device__ inline float objective16(const float* w, const float* h) {
+  float p[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) p[g] = obj_partial(w + 4 * g, h + 4 * g);
+  return canon_zero((p[0] + p[1]) + (p[2] + p[3]));
+}
+
+__global__ void k_score(const float* __restrict__ heads, const uint64_t* __restrict__ ids, uint32_t n,
+                        const QueryDev* __restrict__ qs, uint32_t nq) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t q = blockIdx.y;
+  if (q >= nq) return;
+  const QueryDev* Q = qs + q;
+  if (!Q->active) return;
+  bool pass = false;
+  float o = 0.0f;
+  uint64_t id = 0;
+  if (i < n) {
+    float h[kHeadsPad];
+#pragma unroll
+    for (int k = 0; k < kHeadsPad; ++k) h[k] = heads[(uint64_t)i * kHeadsPad + k];
+    o = objective16(Q->w, h);
+    bool ok = o == o;
+#pragma unroll
+    for (int k = 0; k < kHeadsPad; ++k) ok = ok && h[k] >= Q->lo[k] && h[k] <= Q->hi[k];
+    id = ids[i];
+    pass = ok && key_passes(o, id, Q->st->tau_o, Q->st->tau_id);
+  }
+  if (pass) {
+    const uint32_t idx = atomicAdd(&Q->st->count, 1u);
+    if (idx < Q->cap) {
+      Q->cand_o[idx] = o;
+      Q->cand_id[idx] = id;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix select over a query's candidate buffer. After a pass over a chunk:
+//  - more entries than the buffer holds: the chunk's appends are dropped, the
+//    threshold is raised to the K-th best key among what was written (a valid
+//    lower bound of the final K-th key) and the chunk is flagged for a re-run;
+//  - more than the high-water mark (or `force`): keep exactly the K best keys
+//    (objective desc, id asc), threshold = K-th best key;
+//  - otherwise: nothing but bookkeeping.
+// One workgroup per query.
+// ---------------------------------------------------------------------------
+__device__ inline float unord_f32(uint32_t k) {
+  const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __uint_as_float(u);
+}
+
+__global__ __launch_bounds__(1024) void k_select(const QueryDev* __restrict__ qs, uint32_t chunk_id, int force) {
+  const QueryDev Q = qs[blockIdx.x];
+  if (!Q.active) return;
+  QState* st = Q.st;
+  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t s_digit, s_need, s_eq, s_pos;
+  const uint32_t count = st->count;
+  const uint32_t base = st->chunk_base;
+  const bool over = count > Q.cap;
+  const uint32_t n = over ? Q.cap : count;
+  const uint32_t K = Q.K;
+  const bool run = over || (force ? n > K : count > Q.hwm);
+  __syncthreads();
+  if (!run) {
+    if (tid == 0) {
+      st->appended += count - base;
+      st->chunk_base = count;
+    }
+    return;
+  }
+  // ---- K-th largest order key of the objective ----
+  uint32_t prefix = 0, pmask = 0, need = K;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (uint32_t b = tid; b < 256; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += blockDim.x) {
+      const uint32_t kf = ord_f32(Q.cand_o[i]);
+      if ((kf & pmask) == prefix) atomicAdd(&hist[(kf >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t cum = 0;
+      int b = 255;
+      for (; b > 0; --b) {
+        if (cum + hist[b] >= need) break;
+        cum += hist[b];
+      }
+      s_digit = (uint32_t)b;
+      s_need = need - cum;
+      s_eq = hist[b];
+    }
+    __syncthreads();
+    prefix |= s_digit << shift;
+    pmask |= 255u << shift;
+    need = s_need;
+    __syncthreads();
+  }
+  const uint32_t T = prefix;
+  const uint32_t eq = s_eq;  // entries whose key equals T
+  // ---- among ties on the objective: the `need` smallest ids ----
+  uint64_t I = ~0ull;
+  if (need < eq) {
+    uint64_t ip = 0, im = 0;
+    uint32_t want = need;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (uint32_t b = tid; b < 256; b += blockDim.x) hist[b] = 0;
+      __syncthreads();
+      for (uint32_t i = tid; i < n; i += blockDim.x) {
+        if (ord_f32(Q.cand_o[i]) != T) continue;
+        const uint64_t id = Q.cand_id[i];
+        if ((id & im) == ip) atomicAdd(&hist[(id >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t cum = 0;
+        int b = 0;
+        for (; b < 255; ++b) {
+          if (cum + hist[b] >= want) break;
+          cum += hist[b];
+        }
+        s_digit = (uint32_t)b;
+        s_need = want - cum;
+      }
+      __syncthreads();
+      ip |= (uint64_t)s_digit << shift;
+      im |= 255ull << shift;
+      want = s_need;
+      __syncthreads();
+    }
+    I = ip;
+  }
+  const float To = unord_f32(T);
+  if (over) {
+    if (tid == 0) {
+      st->tau_o = To;
+      st->tau_id = I;
+      st->appended += count - base;
+      st->count = base;
+      st->overflow += 1;
+      Q.rerun[chunk_id] = 1u;
+    }
+    return;
+  }
+  // ---- compaction to exactly K entries ----
+  if (tid == 0) s_pos = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += blockDim.x) {
+    const float o = Q.cand_o[i];
+    const uint32_t kf = ord_f32(o);
+    const uint64_t id = Q.cand_id[i];
+    if (kf > T || (kf == T && id <= I)) {
+      const uint32_t p = atomicAdd(&s_pos, 1u);
+      if (p < K) {
+        Q.tmp_o[p] = o;
+        Q.tmp_id[p] = id;
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < K; i += blockDim.x) {
+    Q.cand_o[i] = Q.tmp_o[i];
+    Q.cand_id[i] = Q.tmp_id[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st->appended += count - base;
+    st->count = K;
+    st->chunk_base = K;
+    st->tau_o = To;
+    st->tau_id = I;
+  }
+}
+
+// Lowers each query's threshold slightly (tau - |tau| 2^-18 - 2^-100) and
+// empties its buffer: used after the sampling pass, whose entries will be met
+// again during the enumeration.
+__global__ void k_tau_relax(const QueryDev* __restrict__ qs, uint32_t nq) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq || !qs[q].active) return;
+  QState* st = qs[q].st;
+  const float t = st->tau_o;
+  if (st->count >= qs[q].K && t == t && t != -INFINITY) {
+    st->tau_o = t - fabsf(t) * 3.814697265625e-06f - 7.888609052210118e-31f;
+    st->tau_id = ~0ull;
+  } else {
+    st->tau_o = -INFINITY;
+    st->tau_id = ~0ull;
+  }
+  st->count = 0;
+  st->chunk_base = 0;
+  st->appended = 0;
+}
+
+// Sort n = min(count, K) entries by (objective desc, id asc): each entry's rank is
+// the number of entries ranked before it (keys are distinct).
+__global__ __launch_bounds__(256) void k_rank_sort(const QueryDev* __restrict__ qs, uint32_t q, float* __restrict__ out_o,
+                                                   uint64_t* __restrict__ out_id) {
+  const QueryDev& Q = qs[q];
+  const uint32_t n = min(Q.st->count, Q.K);
+  __shared__ float so[1024];
+  __shared__ uint64_t sid[1024];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool mine = i < n;
+  const float o = mine ? Q.cand_o[i] : 0.0f;
+  const uint64_t id = mine ? Q.cand_id[i] : 0;
+  uint32_t rank = 0;
+  for (uint32_t t0 = 0; t0 < n; t0 += 1024) {
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < 1024 && t0 + k < n; k += blockDim.x) {
+      so[k] = Q.cand_o[t0 + k];
+      sid[k] = Q.cand_id[t0 + k];
+    }
+    __syncthreads();
+    const uint32_t m = min(1024u, n - t0);
+    if (mine)
+      for (uint32_t k = 0; k < m; ++k) rank += (so[k] > o) || (so[k] == o && sid[k] < id);
+  }
+  if (mine) {
+    out_o[rank] = o;
+    out_id[rank] = id;
+  }
+}
+
+// id -> (reaction, synthon per slot).
+__global__ void k_decode(const ReactDev* __restrict__ react, uint32_t n_react, const uint64_t* __restrict__ ids,
+                         const QState* __restrict__ st, uint32_t K, uint32_t* __restrict__ reaction,
+                         uint32_t* __restrict__ synthon) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = min(st->count, K);
+  if (i >= n) return;
+  const uint64_t id = ids[i];
+  const uint32_t t = find_reaction(react, n_react, id);
+  const ReactDev r = react[t];
+  const uint64_t loc = id - r.id_off;
+  const uint32_t a = (uint32_t)(loc / r.nB), b = (uint32_t)(loc - (uint64_t)a * r.nB);
+  reaction[i] = t;
+  if (r.three) {
+    synthon[3 * i + 0] = a / r.n1;
+    synthon[3 * i + 1] = a % r.n1;
+    synthon[3 * i + 2] = b;
+  } else {
+    synthon[3 * i + 0] = a;
+    synthon[3 * i + 1] = b;
+    synthon[3 * i + 2] = 0;
+  }
+}
+
+// Stratified sample of n distinct compounds of a selection: draw i lies in the
+// i-th of n equal parts of the selection's compound range (SplitMix64 offsets).
+__global__ void k_sample_ids(const SelDev* __restrict__ sel, uint32_t n_sel, const ReactDev* __restrict__ react,
+                             uint64_t total, uint32_t n, uint64_t seed, uint64_t* __restrict__ ids) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t lo = (uint64_t)(((unsigned __int128)total * i) / n);
+  const uint64_t hi = (uint64_t)(((unsigned __int128)total * (i + 1)) / n);
+  uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const uint64_t x = lo + (hi > lo ? z % (hi - lo) : 0);
+  uint32_t a = 0, b = n_sel;
+  while (b - a > 1) {
+    const uint32_t m = (a + b) >> 1;
+    if (sel[m].compound_start <= x) a = m; else b = m;
+  }
+  ids[i] = react[sel[a].t].id_off + (x - sel[a].compound_start);
+}
+
+// Largest |low-precision head - FP32 head| per head.
+__global__ void k_head_err(const float* __restrict__ h_lp, const float* __restrict__ h_32, uint32_t n,
+                           float* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * kHeadsPad) return;
+  atomic_max_nonneg(out + (i % kHeadsPad), fabsf(h_lp[i] - h_32[i]));
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_hoist(const float* U, uint32_t d, uint64_t rows, const float* W1, const float* b1, uint32_t h1,
+                        const uint8_t* is_slot0, float c, float* P, hipStream_t s) {
+  dim3 grid((unsigned)((rows + 63) / 64), (h1 + 63) / 64);
+  hipLaunchKernelGGL(k_hoist, grid, dim3(256), 0, s, U, d, rows, W1, b1, h1, is_slot0, c, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_act_range(const float* P, uint32_t h1, const uint64_t* slot_row0, const uint32_t* slot_size,
+                            uint32_t n_slots_total, const uint32_t* react_slot0, const uint32_t* react_nslots,
+                            uint32_t n_react, int act, float c, float* cmax, float* cmin, float* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_colext, dim3(n_slots_total, (h1 + 127) / 128), dim3(128), 0, s, P, h1, slot_row0, slot_size,
+                     cmax, cmin);
+  hipLaunchKernelGGL(k_actmax, dim3(n_react, (h1 + 127) / 128), dim3(128), 0, s, cmax, cmin, h1, react_slot0,
+                     react_nslots, n_react, act, c, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const float* x, uint64_t n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_absmax, dim3(64), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scales(const float* amax, int prec, int nl, float* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_scales, dim3(1), dim3(64), 0, s, amax, prec, nl, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_frag_x(int prec, const float* W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
+                         const float* mul_dev, float mul, void* out, hipStream_t s) {
+  dim3 grid(256), block(256);
+  if (prec == APEX_PREC_FP32)
+    hipLaunchKernelGGL(k_frag_x<APEX_PREC_FP32>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
+  else if (prec == APEX_PREC_BF16)
+    hipLaunchKernelGGL(k_frag_x<APEX_PREC_BF16>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
+  else
+    hipLaunchKernelGGL(k_frag_x<APEX_PREC_FP8>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, int bf16, float mul, void* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_frag_out_d, dim3(64), dim3(256), 0, s, Wo, H, h2, bf16, mul, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias(const float* b2, uint32_t h2, float c, const float* scal, const float* bo, uint32_t H,
+                       float* b2_out, float* bo_out, hipStream_t s) {
+  const uint32_t n = h2 > kHeadsPad ? h2 : kHeadsPad;
+  hipLaunchKernelGGL(k_bias, dim3((n + 255) / 256), dim3(256), 0, s, b2, h2, c, scal, bo, H, b2_out, bo_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,
+                        hipStream_t s) {
+  if (n == 0 || nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_score, dim3((n + 255) / 256, nq), dim3(256), 0, s, heads, ids, n, qs, nq);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const QueryDev* qs, uint32_t nq, uint32_t chunk_id, int force, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select, dim3(nq), dim3(kSelectThreads), 0, s, qs, chunk_id, force);
+  return hipGetLastError();
+}
+
+hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s) {
+  hipLaunchKernelGGL(k_tau_relax, dim3((nq + 63) / 64), dim3(64), 0, s, qs, nq);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_rank_sort, dim3((K + 255) / 256), dim3(256), 0, s, qs, q, out_o, out_id);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t* ids, const QState* st, uint32_t K,
+                         uint32_t* reaction, uint32_t* synthon, hipStream_t s) {
+  hipLaunchKernelGGL(k_decode, dim3((K + 255) / 256), dim3(256), 0, s, react, n_react, ids, st, K, reaction, synthon);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_ids(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t total, uint32_t n,
+                             uint64_t seed, uint64_t* ids, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_ids, dim3((n + 255) / 256), dim3(256), 0, s, sel, n_sel, react, total, n, seed, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_err(const float* h_lp, const float* h_32, uint32_t n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_head_err, dim3((n * kHeadsPad + 255) / 256), dim3(256), 0, s, h_lp, h_32, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace apex

@@ -1,0 +1,203 @@
+"""Parity of the HIP search (through the C ABI) with the FP64 oracle on seeded
+libraries that span many tiles and ragged edges, in FP32 (exact id sets,
+ties by id), BF16 and FP8 (recall against the oracle, FP32-rescored scores)."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads.gen as g
+from workloads.gen import ACT_RELU, ACT_SILU, Constraint, Query
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from gpu_helpers import device_objects, score_tol
+
+
+def library_scales(lib_h, dec_h, q, n=4096):
+    ids = g.sample_ids(5, "scale_sample", lib_h.n_compounds, n)
+    h = oracle.heads(lib_h, dec_h, ids)
+    return np.sqrt(np.mean(h ** 2, axis=0)), float(np.sqrt(np.mean((h @ q.w.astype(np.float64)) ** 2)))
+
+
+def check_fp32_exact(lib_h, dec_h, q, r, label):
+    ref = oracle.topk(lib_h, dec_h, q, extra=1, near_tol=1e-3)
+    k = min(q.k, ref.n_feasible)
+    print(f"[{label}] n_feasible={ref.n_feasible} gap_k={ref.gap_k:.3e} slack={ref.min_slack_selected:.3e} "
+          f"near={ref.min_violation_near:.3e}", flush=True)
+    assert len(r.ids) == k
+    assert np.array_equal(r.ids, ref.answer_ids), f"{label}: id sets differ"
+    # tolerance 1e-5 relative, with the objective's / head's RMS over a seeded
+    # sample of the library as the floor for values near zero
+    hs, os_ = library_scales(lib_h, dec_h, q)
+    assert np.all(np.abs(r.objective - ref.objective[:k]) <= score_tol(ref.objective[:k], os_))
+    assert np.all(np.abs(r.heads - ref.heads[:k]) <= 1e-5 * np.maximum(np.abs(ref.heads[:k]), hs))
+    rr, ss = oracle.decode(lib_h, r.ids)
+    assert np.array_equal(rr, r.reaction) and np.array_equal(ss, r.synthon)
+    return ref
+
+
+def check_lowp(lib_h, dec_h, q, r, label, min_recall=0.99):
+    ref = oracle.topk(lib_h, dec_h, q)
+    k = min(q.k, ref.n_feasible)
+    got = set(r.ids.tolist())
+    recall = len(got & set(ref.answer_ids.tolist())) / max(k, 1)
+    print(f"[{label}] recall={recall:.4f} n={len(r.ids)} k={k}", flush=True)
+    assert recall >= min_recall
+    # every returned compound is feasible and its FP32-rescored score matches FP64
+    if len(r.ids):
+        h64 = oracle.heads(lib_h, dec_h, r.ids)
+        o64 = h64 @ q.w.astype(np.float64)
+        _, os_ = library_scales(lib_h, dec_h, q)
+        assert np.all(np.abs(r.objective - o64) <= score_tol(o64, os_))
+        for c in q.constraints:
+            assert np.all((h64[:, c.head] >= c.lo - 1e-5) & (h64[:, c.head] <= c.hi + 1e-5))
+        keys = list(zip((-r.objective).tolist(), r.ids.tolist()))
+        assert keys == sorted(keys)
+    return recall
+
+
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c0():
+    lib_h, dec_h, q = g.config_c0()
+    objs = device_objects(lib_h, dec_h)
+    return lib_h, dec_h, q, objs
+
+
+def test_c0_fp32_exact(c0):
+    lib_h, dec_h, q, (lib, dec, eng) = c0
+    print("case: c0 fp32", flush=True)
+    r = eng.search(q, precision="fp32")
+    check_fp32_exact(lib_h, dec_h, q, r, "c0 fp32")
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_c0_low_precision(c0, prec):
+    lib_h, dec_h, q, (lib, dec, eng) = c0
+    print(f"case: c0 {prec}", flush=True)
+    r = eng.search(q, precision=prec)
+    check_lowp(lib_h, dec_h, q, r, f"c0 {prec}")
+
+
+# A library with two- and three-slot reactions and ragged slot sizes, and the
+# benchmark decoder shape (256 -> 512 -> 512 (SiLU) -> 15).
+@pytest.fixture(scope="module")
+def mixed():
+    lib_h = g.make_library(41, [2, 3, 2, 3], [37, 53, 11, 9, 17, 70, 3, 5, 4, 29], 256)
+    dec_h = g.make_decoder(41, [256, 512, 512, 15], ACT_SILU)
+    objs = device_objects(lib_h, dec_h)
+    sample = oracle.heads(lib_h, dec_h, np.arange(0, lib_h.n_compounds, 5, dtype=np.uint64))
+    return lib_h, dec_h, objs, sample
+
+
+def mixed_query(sample, k, q_hi=0.8, reactions=None):
+    w = np.zeros(15, np.float32)
+    w[2] = -1.0
+    w[7] = 0.25
+    cons = [Constraint(6, -math.inf, float(np.float32(np.quantile(sample[:, 6], q_hi)))),
+            Constraint(11, float(np.float32(np.quantile(sample[:, 11], 0.25))), math.inf),
+            Constraint(9, float(np.float32(np.quantile(sample[:, 9], 0.05))),
+                       float(np.float32(np.quantile(sample[:, 9], 0.97))))]
+    return Query(w=w, constraints=cons, k=k, reactions=reactions)
+
+
+@pytest.mark.parametrize("k", [1, 50, 777])
+def test_mixed_fp32_exact(mixed, k):
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print(f"case: mixed fp32 k={k}", flush=True)
+    q = mixed_query(sample, k)
+    r = eng.search(q, precision="fp32")
+    check_fp32_exact(lib_h, dec_h, q, r, f"mixed fp32 k={k}")
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_mixed_low_precision(mixed, prec):
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print(f"case: mixed {prec}", flush=True)
+    q = mixed_query(sample, 200)
+    r = eng.search(q, precision=prec)
+    check_lowp(lib_h, dec_h, q, r, f"mixed {prec}")
+
+
+def test_mixed_subset_and_k_beyond_feasible(mixed):
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print("case: mixed subset", flush=True)
+    q = mixed_query(sample, 5000, reactions=[1, 3])
+    r = eng.search(q, precision="fp32")
+    ref = check_fp32_exact(lib_h, dec_h, q, r, "mixed subset")
+    assert ref.n_feasible < 5000 and len(r.ids) == ref.n_feasible
+
+
+def test_all_infeasible_returns_nothing(mixed):
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print("case: all infeasible", flush=True)
+    q = Query(w=np.ones(15, np.float32), constraints=[Constraint(0, 1e30, math.inf)], k=10)
+    for prec in ("fp32", "bf16", "fp8"):
+        r = eng.search(q, precision=prec)
+        assert len(r.ids) == 0
+
+
+def test_forced_chunks_and_overflow_reruns(mixed):
+    """Many small chunks and a tiny candidate buffer (forced from the host) give
+    the same answer; the overflow path re-runs chunks."""
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print("case: forced chunks + overflow", flush=True)
+    q = mixed_query(sample, 300, q_hi=0.95)
+    base = eng.search(q, precision="fp32")
+    os.environ["APEX_TEST_CHUNK"] = "2048"
+    os.environ["APEX_TEST_CAP"] = "700"
+    try:
+        r = eng.search(q, precision="fp32")
+    finally:
+        del os.environ["APEX_TEST_CHUNK"]
+        del os.environ["APEX_TEST_CAP"]
+    print(f"reruns={r.n_reruns} candidates={r.n_candidates}", flush=True)
+    assert r.n_reruns > 0
+    assert np.array_equal(r.ids, base.ids) and np.array_equal(r.objective, base.objective)
+    check_fp32_exact(lib_h, dec_h, q, r, "forced")
+
+
+def test_fused_batch_equals_single(mixed):
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print("case: fused batch", flush=True)
+    qs = [mixed_query(sample, 100), mixed_query(sample, 10, q_hi=0.6, reactions=[0, 2]),
+          Query(w=np.eye(15, dtype=np.float32)[4], constraints=[], k=333)]
+    for prec in ("fp32", "bf16"):
+        fused = eng.search_batch(qs, precision=prec)
+        for q, f in zip(qs, fused):
+            single = eng.search(q, precision=prec)
+            assert np.array_equal(f.ids, single.ids) and np.array_equal(f.objective, single.objective)
+
+
+def test_ties_lower_id_wins():
+    """Duplicated synthon rows give identical scores; lower ids rank first."""
+    print("case: ties", flush=True)
+    lib_h = g.make_library(43, [2], [40, 33], 64)
+    lib_h.tables[5] = lib_h.tables[1]
+    lib_h.tables[9] = lib_h.tables[1]
+    lib_h.tables[40 + 7] = lib_h.tables[40 + 2]
+    dec_h = g.make_decoder(43, [64, 128, 5], ACT_RELU)
+    lib, dec, eng = device_objects(lib_h, dec_h, precisions=("fp32",))
+    q = Query(w=np.array([1, 0, 0, 0, 0], np.float32), constraints=[], k=600)
+    r = eng.search(q, precision="fp32")
+    check_fp32_exact(lib_h, dec_h, q, r, "ties")
+    o = r.objective
+    assert any(o[i] == o[i + 1] for i in range(len(o) - 1))
+
+
+def test_ids_beyond_32_bits():
+    """A first reaction of 4.9e9 compounds pushes the second reaction's ids past
+    2^32; a subset query on the second reaction returns the exact ids."""
+    print("case: 64-bit ids", flush=True)
+    lib_h = g.make_library(47, [2, 2], [70000, 70000, 30, 45], 64)
+    dec_h = g.make_decoder(47, [64, 128, 5], ACT_RELU)
+    lib, dec, eng = device_objects(lib_h, dec_h, precisions=("fp32",))
+    q = Query(w=np.array([0, 1, 0, 0, 0], np.float32), constraints=[], k=40, reactions=[1])
+    r = eng.search(q, precision="fp32")
+    assert r.ids.min() >= 70000 * 70000 > 2 ** 32
+    check_fp32_exact(lib_h, dec_h, q, r, "64-bit ids")
