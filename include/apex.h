@@ -225,6 +225,15 @@ apex_status apex_server_cancel(apex_server* srv, uint64_t ticket);
 apex_status apex_server_stats_get(apex_server* srv, apex_server_stats* out);
 apex_status apex_server_destroy(apex_server* srv);
 
+/* Heads of listed compounds, evaluated with the enumeration arithmetic of one
+ * precision (FP32, or BF16/FP8 before rescoring): the per-slot rows are
+ * combined in FP32 and the decoder runs on MFMA. ids: device [n] compound ids;
+ * heads: device [n x 16] FP32, columns >= H are 0; an id >= the library size
+ * yields a row of NaN. Asynchronous on `stream`. Errors: APEX_E_INVALID (NULL
+ * pointers, precision not enabled), APEX_E_DEVICE. */
+apex_status apex_engine_heads(apex_engine* eng, const uint64_t* ids, uint32_t n, uint32_t precision, float* heads,
+                              void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Kernel timing                                                             */
 /* ------------------------------------------------------------------------ */
@@ -232,9 +241,9 @@ apex_status apex_server_destroy(apex_server* srv);
  * turns timing on (enable != 0) or off. While on, every launch of that kernel
  * during apex_search / apex_search_batch is bracketed by HIP events on the
  * search stream; *ms is the summed event time, *launches the launch count and
- * *compounds the compounds those launches covered (tiles x tile size, ragged
- * tiles included). Any output pointer may be NULL. Host only, not thread-safe
- * with a concurrent search on the same engine. */
+ * *compounds the library compounds those launches evaluated. Any output
+ * pointer may be NULL. Host only; not safe to call during a concurrent search
+ * on the same engine. */
 apex_status apex_engine_profile(apex_engine* eng, int enable, double* ms, uint64_t* launches, uint64_t* compounds);
 
 /* ------------------------------------------------------------------------ */

@@ -108,6 +108,14 @@ static void layout(const orc_library* L, uint32_t* slot_base, uint64_t* row_base
   offset[L->n_reactions] = off;
 }
 
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 uint64_t orc_num_compounds(const orc_library* L) {
   uint64_t total = 0;
   uint32_t sb = 0;

@@ -71,6 +71,8 @@ def _load():
         lib.orc_topk.restype = ctypes.c_int
         lib.orc_topk_lex.argtypes = [P, P, P, P, P, P]
         lib.orc_topk_lex.restype = ctypes.c_int
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -114,6 +116,11 @@ def _query_struct(q, n_reactions: int, keep: _Keep) -> _Query:
         subset = keep.ptr(m)
     return _Query(keep.ptr(w), len(q.constraints), keep.ptr(heads), keep.ptr(lo), keep.ptr(hi),
                   int(q.k), subset)
+
+
+def max_threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(_load().orc_max_threads())
 
 
 def num_compounds(lib) -> int:

@@ -88,6 +88,7 @@ _SIGS = {
     "apex_batch_workspace_size": [P, P, U32, P],
     "apex_search_batch": [P, P, U32, P, ctypes.c_size_t, P, P],
     "apex_engine_profile": [P, ctypes.c_int, P, P, P],
+    "apex_engine_heads": [P, P, U32, U32, P, P],
     "apex_server_create": [P, P, P],
     "apex_server_submit": [P, P, P],
     "apex_server_poll": [P, U64, P, ctypes.c_int],
@@ -298,6 +299,15 @@ class Engine:
             r.c = rc
             out.append(r.result())
         return out
+
+    def heads(self, ids, precision: str = "fp32", stream: Optional[torch.cuda.Stream] = None) -> np.ndarray:
+        """Heads of the listed compounds in one precision's enumeration arithmetic."""
+        ids_d = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int64)).cuda()
+        out = torch.empty((max(len(ids), 1), 16), dtype=torch.float32, device="cuda")
+        _check(lib().apex_engine_heads(self.handle, ids_d.data_ptr(), len(ids), PREC[precision], out.data_ptr(),
+                                       _stream_ptr(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        return out[:len(ids), :self.n_heads].cpu().numpy()
 
     def profile(self, enable: bool):
         """Returns (ms, launches, compounds) timed since the last call, then

@@ -100,6 +100,7 @@ struct EnumArgs {
   const uint64_t* ids;     // compound ids
   uint32_t n_ids;
   uint64_t n_reactions;
+  uint64_t n_total;        // compounds in the library
   float* heads_out;        // [n_ids][16]
 };
 

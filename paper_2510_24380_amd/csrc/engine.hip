@@ -292,6 +292,7 @@ apex_status apex::engine_gather(apex_engine* E, int prec, const uint64_t* ids, u
   a.ids = ids;
   a.n_ids = n;
   a.n_reactions = E->lib->T;
+  a.n_total = E->lib->total;
   a.heads_out = heads;
   const uint32_t per = kWaves * enum_rows_per_block_wave(prec) * 16;
   const uint32_t grid = (n + per - 1) / per;
@@ -461,4 +462,12 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
 extern "C" apex_status apex_engine_destroy(apex_engine* eng) {
   delete eng;
   return APEX_OK;
+}
+
+extern "C" apex_status apex_engine_heads(apex_engine* eng, const uint64_t* ids, uint32_t n, uint32_t precision,
+                                         float* heads, void* stream) {
+  if (!eng || (n && (!ids || !heads))) return set_error(APEX_E_INVALID, "null argument");
+  if (precision > APEX_PREC_FP8 || !eng->prec[precision].on)
+    return set_error(APEX_E_INVALID, "precision %u not enabled in this engine", precision);
+  return engine_gather(eng, (int)precision, ids, n, heads, (hipStream_t)stream);
 }

@@ -288,7 +288,10 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
         const uint32_t t = find_reaction(A.react, (uint32_t)A.n_reactions, id);
         const ReactDev rr = A.react[t];
         const uint64_t loc = id - rr.id_off;
-        const uint32_t a = (uint32_t)(loc / rr.nB), b = (uint32_t)(loc - (uint64_t)a * rr.nB);
+        // ids past the library end are clamped to rows in bounds (reported as NaN)
+        const uint64_t a64 = loc / rr.nB;
+        const uint32_t a = a64 < rr.nA ? (uint32_t)a64 : rr.nA - 1;
+        const uint32_t b = (uint32_t)(loc % rr.nB);
         if (rr.three) {
           const uint32_t i0 = a / rr.n1, i1 = a - i0 * rr.n1;
           pa = A.P + (uint64_t)(rr.row0 + i0) * H1 + g * KG;
@@ -445,6 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
       for (int r = 0; r < R; ++r)
         if (valid[r]) {
           float4 o4 = make_float4(heads[r][0], heads[r][1], heads[r][2], heads[r][3]);
+          if (A.ids[cid[r]] >= A.n_total) o4 = make_float4(NAN, NAN, NAN, NAN);
           *reinterpret_cast<float4*>(A.heads_out + cid[r] * 16 + 4 * g) = o4;
         }
     } else {

@@ -379,25 +379,6 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   EventPool evp;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
   std::vector<uint64_t> timed_comp;
-  auto enum_chunk = [&](uint64_t v0, uint64_t v1) -> apex_status {
-    a.tile_begin = v0;
-    a.tile_end = v1;
-    const uint64_t nt = v1 - v0;
-    const uint32_t grid = nt < grid_full ? (uint32_t)nt : grid_full;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (E->profile) {
-      e0 = evp.get();
-      e1 = evp.get();
-      if (e0) HIP_TRY(hipEventRecord(e0, s));
-    }
-    HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, false, a, grid, s));
-    if (E->profile && e0 && e1) {
-      HIP_TRY(hipEventRecord(e1, s));
-      timed.emplace_back(e0, e1);
-      timed_comp.push_back(nt * tile_compounds(prec));
-    }
-    return APEX_OK;
-  };
   auto chunk_compounds = [&](uint64_t v0, uint64_t v1) -> uint64_t {
     // compounds of the selection inside tiles [v0, v1) (ragged tiles counted exactly)
     uint64_t c = 0;
@@ -419,6 +400,25 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
       }
     }
     return c;
+  };
+  auto enum_chunk = [&](uint64_t v0, uint64_t v1) -> apex_status {
+    a.tile_begin = v0;
+    a.tile_end = v1;
+    const uint64_t nt = v1 - v0;
+    const uint32_t grid = nt < grid_full ? (uint32_t)nt : grid_full;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (E->profile) {
+      e0 = evp.get();
+      e1 = evp.get();
+      if (e0) HIP_TRY(hipEventRecord(e0, s));
+    }
+    HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, false, a, grid, s));
+    if (E->profile && e0 && e1) {
+      HIP_TRY(hipEventRecord(e1, s));
+      timed.emplace_back(e0, e1);
+      timed_comp.push_back(chunk_compounds(v0, v1));
+    }
+    return APEX_OK;
   };
   for (size_t c = 0; c < chunks.size(); ++c) {
     apex_status st = enum_chunk(chunks[c].first, chunks[c].second);

@@ -7,6 +7,8 @@
    compounds. A "stringent" variant uses quantiles in [0.2, 0.4].
 2. c1_oracle_<variant>.json: the FP64 oracle's exhaustive top-k (k = 1000, plus
    one extra entry for the k-th gap) with its boundary margins.
+3. c1_heads_sample.json: FP64 heads of 1024 seeded compounds (per-head error of
+   the low-precision paths).
 
 Only the oracle computes anything here. Run: python tests/golden/make_c1_golden.py
 (about 8 minutes per variant on 8 cores).
@@ -67,7 +69,14 @@ def main():
         json.dump({"source": "tests/golden/make_c1_golden.py (FP64 oracle head quantiles, 2^16 seeded compounds)",
                    "seed": SEED, "n_compounds": lib.n_compounds, "queries": queries},
                   open(qpath, "w"), indent=1)
-    only = sys.argv[1:] or list(queries)
+    hpath = os.path.join(HERE, "c1_heads_sample.json")
+    if not os.path.exists(hpath):
+        ids = g.sample_ids(SEED, "c1_head_error_sample", lib.n_compounds, 1024)
+        H = oracle.heads(lib, dec, ids)
+        json.dump({"source": "FP64 oracle heads of 1024 seeded compounds, tests/golden/make_c1_golden.py",
+                   "ids": [int(x) for x in ids], "heads": [[float(v) for v in row] for row in H]},
+                  open(hpath, "w"))
+    only = sys.argv[1:] or [v for v in queries if not os.path.exists(os.path.join(HERE, f"c1_oracle_{v}.json"))]
     for variant in only:
         q = to_query(queries[variant])
         t0 = time.time()

@@ -30,12 +30,19 @@ def check_fp32_exact(lib_h, dec_h, q, r, label):
     print(f"[{label}] n_feasible={ref.n_feasible} gap_k={ref.gap_k:.3e} slack={ref.min_slack_selected:.3e} "
           f"near={ref.min_violation_near:.3e}", flush=True)
     assert len(r.ids) == k
-    assert np.array_equal(r.ids, ref.answer_ids), f"{label}: id sets differ"
+    # exact id set; order may differ only between compounds whose FP64
+    # objectives are closer than float32 rounding
+    assert set(r.ids.tolist()) == set(ref.answer_ids.tolist()), f"{label}: id sets differ"
+    pos = {int(i): n for n, i in enumerate(ref.answer_ids.tolist())}
+    perm = np.array([pos[int(i)] for i in r.ids.tolist()], dtype=np.int64)
+    o_ref, h_ref = ref.objective[:k][perm], ref.heads[:k][perm]
     # tolerance 1e-5 relative, with the objective's / head's RMS over a seeded
     # sample of the library as the floor for values near zero
     hs, os_ = library_scales(lib_h, dec_h, q)
-    assert np.all(np.abs(r.objective - ref.objective[:k]) <= score_tol(ref.objective[:k], os_))
-    assert np.all(np.abs(r.heads - ref.heads[:k]) <= 1e-5 * np.maximum(np.abs(ref.heads[:k]), hs))
+    tol = score_tol(o_ref, os_)
+    assert np.all(np.abs(r.objective - o_ref) <= tol)
+    assert all(o_ref[i] >= o_ref[i + 1] - 2 * tol[i] for i in range(len(o_ref) - 1))
+    assert np.all(np.abs(r.heads - h_ref) <= 1e-5 * np.maximum(np.abs(h_ref), hs))
     rr, ss = oracle.decode(lib_h, r.ids)
     assert np.array_equal(rr, r.reaction) and np.array_equal(ss, r.synthon)
     return ref
