@@ -110,10 +110,14 @@ typedef struct {
 
 /* Keeps non-owning references to the weights until every engine using the
  * decoder has been created (engines copy what they need). Supported shapes
- * (else APEX_E_UNSUPPORTED): H = dims[n_layers] <= APEX_MAX_HEADS; the first
- * hidden width dims[1] is 128, 256 or 512; with three layers the second hidden
- * width dims[2] is a multiple of 32 up to 512. Errors: APEX_E_INVALID for NULL
- * pointers, n_layers outside 1..3, a zero width or an unknown activation. */
+ * (else APEX_E_UNSUPPORTED): H = dims[n_layers] <= APEX_MAX_HEADS; with two or
+ * three layers the first hidden width dims[1] is 128, 256 or 512, and with three
+ * layers the second hidden width dims[2] is a multiple of 32 up to 512. One
+ * layer is the paper's linear probe: every head is a sum of per-synthon
+ * contributions plus its bias (eq. "apex"); such engines run in FP32 only (no
+ * matrix layer is left after the first layer is applied per synthon). Errors:
+ * APEX_E_INVALID for NULL pointers, n_layers outside 1..3, a zero width or an
+ * unknown activation. */
 apex_status apex_decoder_create(const apex_decoder_desc* desc, apex_decoder** out);
 apex_status apex_decoder_destroy(apex_decoder* dec);
 

@@ -8,5 +8,6 @@ from .binding import (  # noqa: F401
     Engine,
     Library,
     SearchResult,
+    Server,
     lib,
 )

@@ -323,3 +323,54 @@ class Engine:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.apex_engine_destroy(self.handle)
             self.handle = None
+
+
+class Server:
+    """Continuous-batching server over one engine (apex_server_*): a library
+    thread admits queries by workspace memory and fuses those that are active
+    into chunk-by-chunk passes. The pool is device memory owned by this object."""
+
+    def __init__(self, engine: Engine, pool_bytes: int, max_active: int = 8, chunk_compounds: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.engine = engine
+        self.pool = torch.empty(max(int(pool_bytes), 256), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        cfg = ServerConfigC(self.pool.data_ptr(), self.pool.numel(), int(max_active), int(self.stream.cuda_stream),
+                            int(chunk_compounds))
+        h = P()
+        _check(lib().apex_server_create(engine.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._k = {}
+
+    def submit(self, q, precision: str = "fp32", pool_factor: int = 0) -> int:
+        m = _QueryMarshal(q, self.engine.n_heads, precision, pool_factor)
+        t = U64()
+        _check(lib().apex_server_submit(self.handle, ctypes.byref(m.c), ctypes.byref(t)))
+        self._k[int(t.value)] = int(q.k)
+        return int(t.value)
+
+    def poll(self, ticket: int, timeout_ms: int = -1) -> Optional[SearchResult]:
+        """The result, or None while the query is still pending."""
+        r = _ResultMarshal(self._k[ticket], self.engine.n_heads)
+        st = lib().apex_server_poll(self.handle, ticket, ctypes.byref(r.c), int(timeout_ms))
+        if st == -5:
+            return None
+        self._k.pop(ticket, None)
+        _check(st)
+        return r.result()
+
+    def cancel(self, ticket: int) -> None:
+        _check(lib().apex_server_cancel(self.handle, ticket))
+
+    def stats(self) -> dict:
+        s = ServerStatsC()
+        _check(lib().apex_server_stats_get(self.handle, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in ServerStatsC._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.apex_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

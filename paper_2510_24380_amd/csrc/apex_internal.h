@@ -7,22 +7,25 @@
 
 namespace apex {
 
-constexpr int kWaves = 8;              // waves per workgroup of the fused kernel
-constexpr int kThreads = kWaves * 64;  // 512
 constexpr int kRowPad = 4;             // LDS row padding (floats) for staged synthon rows
 constexpr int kHeadsPad = 16;          // heads are padded to one 16-wide MFMA tile
 constexpr uint32_t kSelectThreads = 1024;
 
-// Tile geometry per precision: every wave holds R blocks of 16 compounds. A block
-// is one "A" row (slot 0, or slots 0 and 1 for three-slot reactions) against 16
-// consecutive "B" rows (the last slot).
+// Workgroup and tile geometry of the fused kernel per precision. Every wave
+// holds R blocks of 16 compounds; a block is one "A" row (slot 0, or slots 0 and
+// 1 of a three-slot reaction) against 16 consecutive "B" rows (the last slot).
+// A tile is TA A-rows x 16 B-rows. BF16 and FP8 use 4-wave workgroups small
+// enough in LDS for two to share a CU.
 template <int PREC> struct TileShape;
-template <> struct TileShape<APEX_PREC_FP32> { static constexpr int R = 1, TA = 8, NB = 1; };
-template <> struct TileShape<APEX_PREC_BF16> { static constexpr int R = 2, TA = 16, NB = 1; };
-template <> struct TileShape<APEX_PREC_FP8> { static constexpr int R = 4, TA = 16, NB = 2; };
+template <> struct TileShape<APEX_PREC_FP32> { static constexpr int W = 8, R = 1, TA = 8; };
+template <> struct TileShape<APEX_PREC_BF16> { static constexpr int W = 4, R = 2, TA = 8; };
+template <> struct TileShape<APEX_PREC_FP8> { static constexpr int W = 4, R = 3, TA = 12; };
+constexpr int kTileB = 16;
 
-inline int tile_ta(int prec) { return prec == APEX_PREC_FP32 ? 8 : 16; }
-inline int tile_tb(int prec) { return prec == APEX_PREC_FP8 ? 32 : 16; }
+inline int tile_ta(int prec) { return prec == APEX_PREC_FP32 ? 8 : (prec == APEX_PREC_BF16 ? 8 : 12); }
+inline int tile_tb(int) { return kTileB; }
+inline int enum_waves(int prec) { return prec == APEX_PREC_FP32 ? 8 : 4; }
+inline int enum_rows(int prec) { return prec == APEX_PREC_FP32 ? 1 : (prec == APEX_PREC_BF16 ? 2 : 3); }
 
 // One reaction of the library as the kernels see it: every compound is a pair
 // (a, b) with a over the first slot(s) and b over the last slot.

@@ -160,9 +160,8 @@ extern "C" apex_status apex_decoder_create(const apex_decoder_desc* desc, apex_d
     if (!desc->W[l] || !desc->b[l]) return set_error(APEX_E_INVALID, "layer %u has a null pointer", l);
   const uint32_t H = desc->dims[L];
   if (H > APEX_MAX_HEADS) return set_error(APEX_E_UNSUPPORTED, "H = %u > %d heads", H, APEX_MAX_HEADS);
-  if (L == 1) return set_error(APEX_E_UNSUPPORTED, "one-layer (linear probe) decoders are not built in yet");
   const uint32_t h1 = desc->dims[1];
-  if (h1 != 128 && h1 != 256 && h1 != 512)
+  if (L >= 2 && h1 != 128 && h1 != 256 && h1 != 512)
     return set_error(APEX_E_UNSUPPORTED, "first hidden width %u (128, 256 or 512 supported)", h1);
   if (L == 3 && (desc->dims[2] % 32 != 0 || desc->dims[2] > 512))
     return set_error(APEX_E_UNSUPPORTED, "second hidden width %u (multiple of 32, <= 512)", desc->dims[2]);
@@ -203,8 +202,12 @@ float act_prescale(uint32_t act) { return act == APEX_ACT_SILU ? -1.442695040888
 
 int elem_bytes(int p) { return p == APEX_PREC_FP32 ? 4 : (p == APEX_PREC_BF16 ? 2 : 1); }
 
+// Width of the hoisted rows: the first hidden layer, or the 16 padded heads of a
+// one-layer (linear) decoder.
+uint32_t hoist_width(const apex_decoder* D) { return D->L == 1 ? (uint32_t)kHeadsPad : D->dims[1]; }
+
 void engine_layout(apex_engine* E, const apex_library* L, const apex_decoder* D, uint32_t mask, Bump& b) {
-  const uint32_t H1 = D->dims[1];
+  const uint32_t H1 = hoist_width(D);
   const uint32_t H2 = D->L == 3 ? D->dims[2] : 0;
   const uint32_t nslots = (uint32_t)L->slot_sizes.size();
   E->P = b.take<float>((size_t)L->rows * H1);
@@ -273,6 +276,8 @@ extern "C" apex_status apex_engine_workspace_size(const apex_library* lib, const
   if (!lib || !dec || !bytes) return set_error(APEX_E_INVALID, "null argument");
   if (precisions == 0 || (precisions & ~7u)) return set_error(APEX_E_INVALID, "precisions mask 0x%x", precisions);
   if (dec->dims[0] != lib->d) return set_error(APEX_E_INVALID, "decoder input %u != library d %u", dec->dims[0], lib->d);
+  if (dec->L == 1 && (precisions & ~APEX_PREC_MASK(APEX_PREC_FP32)))
+    return set_error(APEX_E_UNSUPPORTED, "a one-layer decoder has no matrix layer: FP32 only");
   apex_engine tmp;
   Bump b(nullptr);
   engine_layout(&tmp, lib, dec, precisions | APEX_PREC_MASK(APEX_PREC_FP32), b);
@@ -294,7 +299,7 @@ apex_status apex::engine_gather(apex_engine* E, int prec, const uint64_t* ids, u
   a.n_reactions = E->lib->T;
   a.n_total = E->lib->total;
   a.heads_out = heads;
-  const uint32_t per = kWaves * enum_rows_per_block_wave(prec) * 16;
+  const uint32_t per = enum_waves(prec) * enum_rows(prec) * 16;
   const uint32_t grid = (n + per - 1) / per;
   HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, true, a, grid, s));
   return APEX_OK;
@@ -313,12 +318,12 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
   hipStream_t s = (hipStream_t)stream;
   auto* E = new apex_engine();
   E->lib = lib;
-  E->H1 = dec->dims[1];
+  E->H1 = hoist_width(dec);
   E->H2 = dec->L == 3 ? dec->dims[2] : 0;
   E->NL = dec->L - 1;
   E->H = dec->dims[dec->L];
-  E->act = dec->act;
-  E->c_act = act_prescale(dec->act);
+  E->act = dec->L == 1 ? (uint32_t)APEX_ACT_NONE : dec->act;  // no activation without a hidden layer
+  E->c_act = act_prescale(E->act);
   E->dims = dec->dims;
   E->mask = precisions | APEX_PREC_MASK(APEX_PREC_FP32);
   E->user_mask = precisions;
@@ -373,7 +378,8 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
   if (he != hipSuccess) return fail(set_error(APEX_E_DEVICE, "upload: %s", hipGetErrorString(he)));
 
   // hoist of the first layer (with its bias on slot-0 rows) and the activation prescale
-  he = launch_hoist(lib->tables, lib->d, lib->rows, dec->W[0], dec->b[0], E->H1, E->is_slot0, E->c_act, E->P, s);
+  he = launch_hoist(lib->tables, lib->d, lib->rows, dec->W[0], dec->b[0], dec->dims[1], E->H1, E->is_slot0,
+                    E->c_act, E->P, s);
   if (he != hipSuccess) return fail(set_error(APEX_E_DEVICE, "hoist: %s", hipGetErrorString(he)));
 
   const float* W2 = dec->L == 3 ? dec->W[1] : nullptr;
@@ -402,10 +408,12 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
         if (he == hipSuccess)
           he = launch_frag_out_d(Wo, E->H, E->H2, p != APEX_PREC_FP32, 1.0f / E->c_act, S.wo, s);
         if (he == hipSuccess) he = launch_bias(b2, E->H2, E->c_act, S.scal, bo, E->H, S.b2, S.bo, s);
-      } else {
+      } else if (E->NL == 1) {
         he = launch_frag_x(p, Wo, E->H, E->H1, 1, p == APEX_PREC_FP8 ? S.scal + 4 : nullptr, 1.0f / E->c_act,
                            S.wo, s);
         if (he == hipSuccess) he = launch_bias(nullptr, 0, E->c_act, S.scal, bo, E->H, nullptr, S.bo, s);
+      } else {  // linear decoder: its bias is already in the slot-0 rows
+        he = launch_bias(nullptr, 0, 1.0f, S.scal, nullptr, 0, nullptr, S.bo, s);
       }
     }
     if (he != hipSuccess) return fail(set_error(APEX_E_DEVICE, "weight preparation: %s", hipGetErrorString(he)));

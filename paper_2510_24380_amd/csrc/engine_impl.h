@@ -71,6 +71,19 @@ struct apex_engine {
   bool profile = false;
   double prof_ms = 0.0;
   uint64_t prof_launches = 0, prof_compounds = 0;
+  struct Timed {
+    hipEvent_t a, b;
+    uint64_t compounds;
+  };
+  std::vector<hipEvent_t> ev_free;
+  std::vector<Timed> ev_pending;
+  ~apex_engine() {
+    for (auto e : ev_free) (void)hipEventDestroy(e);
+    for (auto& t : ev_pending) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+  }
 };
 
 namespace apex {

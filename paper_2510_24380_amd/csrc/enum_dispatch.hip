@@ -15,10 +15,7 @@ static const void* enum_kernel(int prec, int h1, int nl, int act, bool gather) {
   return nullptr;
 }
 
-int enum_rows_per_block_wave(int prec) {
-  return prec == APEX_PREC_FP32 ? TileShape<APEX_PREC_FP32>::R
-                                : (prec == APEX_PREC_BF16 ? TileShape<APEX_PREC_BF16>::R : TileShape<APEX_PREC_FP8>::R);
-}
+int enum_rows_per_block_wave(int prec) { return enum_rows(prec); }
 
 hipError_t enum_prepare(int prec, int h1, int nl, int act, bool gather, uint32_t h2, int* max_wg_per_cu) {
   const void* k = enum_kernel(prec, h1, nl, act, gather);
@@ -28,7 +25,7 @@ hipError_t enum_prepare(int prec, int h1, int nl, int act, bool gather, uint32_t
   if (e != hipSuccess) return e;
   if (max_wg_per_cu) {
     int n = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kThreads, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, enum_waves(prec) * 64, lds);
     if (e != hipSuccess) return e;
     *max_wg_per_cu = n;
   }
@@ -41,7 +38,7 @@ hipError_t launch_enum(int prec, int h1, int nl, int act, bool gather, const Enu
   if (!k) return hipErrorInvalidValue;
   const int lds = enum_lds_bytes(prec, h1, nl, (int)a.H2, gather);
   void* args[] = {const_cast<EnumArgs*>(&a)};
-  return hipLaunchKernel(k, dim3(grid), dim3(kThreads), args, (size_t)lds, s);
+  return hipLaunchKernel(k, dim3(grid), dim3(enum_waves(prec) * 64), args, (size_t)lds, s);
 }
 
 }  // namespace apex

@@ -17,6 +17,8 @@ namespace apex {
   if (h1 == 512) { APEX_NLS(512, G) }
 
 const void* enum_kernel_fp32(int h1, int nl, int act, bool gather) {
+  if (nl == 0 && h1 == 16 && act == APEX_ACT_NONE)  // one-layer (linear) decoder
+    return gather ? APEX_K(16, 0, APEX_ACT_NONE, true) : APEX_K(16, 0, APEX_ACT_NONE, false);
   if (gather) { APEX_H1S(true) } else { APEX_H1S(false) }
   return nullptr;
 }

@@ -128,15 +128,19 @@ __device__ __forceinline__ typename MfmaT<PREC>::frag load_frag(const unsigned c
   return *reinterpret_cast<const F*>(p);
 }
 
-// LDS bytes the fused kernel needs (host and device agree on this).
+// LDS bytes the fused kernel needs (host and device agree on this). The staged
+// synthon rows (activation phase) and the double-buffered GEMM weight chunks
+// (GEMM phase) share one region; the final-layer fragments and the GEMM start
+// values stay resident.
 __host__ __device__ constexpr int enum_lds_bytes(int prec, int h1, int nl, int h2, bool gather) {
   int eb = prec == APEX_PREC_FP32 ? 4 : (prec == APEX_PREC_BF16 ? 2 : 1);
-  int ta = prec == APEX_PREC_FP32 ? 8 : 16;
-  int tb = prec == APEX_PREC_FP8 ? 32 : 16;
-  int rows = gather ? 0 : (ta + tb) * (h1 + kRowPad) * 4;
+  int ta = prec == APEX_PREC_FP32 ? 8 : (prec == APEX_PREC_BF16 ? 8 : 12);
+  int rows = gather ? 0 : (ta + kTileB) * (h1 + kRowPad) * 4;
   int chunk = nl == 2 ? 2 * 16 * h1 * eb : 0;
-  int wo = nl == 2 ? 16 * h2 * (prec == APEX_PREC_FP32 ? 4 : 2) : 16 * h1 * eb;
-  return rows + chunk + wo;
+  int region = rows > chunk ? rows : chunk;
+  int wo = nl == 2 ? 16 * h2 * (prec == APEX_PREC_FP32 ? 4 : 2) : (nl == 1 ? 16 * h1 * eb : 0);
+  int b2 = nl == 2 ? h2 * 4 : 0;
+  return region + wo + b2;
 }
 
 __device__ __forceinline__ uint32_t find_reaction(const ReactDev* react, uint32_t n, uint64_t id) {
@@ -158,28 +162,34 @@ __device__ __forceinline__ uint32_t find_sel(const SelDev* sel, uint32_t n, uint
 }
 
 template <int PREC, int H1, int NL, int ACT, bool GATHER>
-__global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
+__global__ __launch_bounds__(TileShape<PREC>::W * 64)
+__attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
   using M = MfmaT<PREC>;
   using TS = TileShape<PREC>;
   using Frag = typename M::frag;
-  constexpr int R = TS::R, TA = TS::TA, NB = TS::NB, TB = 16 * NB;
+  constexpr int W = TS::W, T = W * 64;
+  constexpr int R = TS::R, TA = TS::TA, TB = kTileB;
   constexpr int E = M::E;
   constexpr int NS = H1 / M::KS;  // k-steps over the first hidden width
   constexpr int KG = H1 / 4;      // activations per lane group
   constexpr int ROW = H1 + kRowPad;
   constexpr int CHUNK = 16 * H1 * M::EB;  // bytes of one 16-neuron GEMM weight chunk
-  constexpr int NPRE = (CHUNK / 16 + kThreads - 1) / kThreads;
+  constexpr int NPRE = (CHUNK / 16 + T - 1) / T;
+  constexpr int ROWS_BYTES = GATHER ? 0 : (TA + TB) * ROW * 4;
+  constexpr int REGION = ROWS_BYTES > (NL == 2 ? 2 * CHUNK : 0) ? ROWS_BYTES : (NL == 2 ? 2 * CHUNK : 0);
   static_assert(NS * E == KG, "layout");
-  static_assert(TA * NB == kWaves * R, "tile");
+  static_assert(TA == W * R, "tile");
 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   float* sA = reinterpret_cast<float*>(smem);
-  float* sB = sA + (GATHER ? 0 : TA * ROW);
-  unsigned char* sW = reinterpret_cast<unsigned char*>(sB + (GATHER ? 0 : TB * ROW));
-  unsigned char* sWo = sW + (NL == 2 ? 2 * CHUNK : 0);
+  float* sB = sA + TA * ROW;
+  unsigned char* sW = smem;  // GEMM weight chunks share the region with the staged rows
+  unsigned char* sWo = smem + REGION;
+  const uint32_t H2 = NL == 2 ? A.H2 : 0;
+  float* sB2 = reinterpret_cast<float*>(
+      sWo + (NL == 2 ? 16 * H2 * (PREC == APEX_PREC_FP32 ? 4 : 2) : (NL == 1 ? 16 * H1 * M::EB : 0)));
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
-  const uint32_t H2 = NL == 2 ? A.H2 : 0;
   const int NC = NL == 2 ? (int)(H2 / 16) : 0;
   const float S2 = A.pd.scal[0], So = A.pd.scal[1], XS = A.pd.scal[2];
 
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
     const uint32_t per_xcd = G / 8;
     const uint32_t wg = (G % 8 == 0) ? (bid % 8) * per_xcd + bid / 8 : bid;
     if (GATHER) {
-      const uint64_t per_wg = kWaves * R * 16;
+      const uint64_t per_wg = W * R * 16;
       v = (uint64_t)wg * per_wg;
       vend = v + per_wg;
       if (v >= A.n_ids) return;
@@ -205,12 +215,14 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
     }
   }
 
-  // Final-layer fragments stay in LDS for the whole launch.
+  // Final-layer fragments and GEMM start values stay in LDS for the whole launch.
   {
-    const int wo_bytes = NL == 2 ? 16 * (int)H2 * (PREC == APEX_PREC_FP32 ? 4 : 2) : 16 * H1 * M::EB;
+    const int wo_bytes = NL == 2 ? 16 * (int)H2 * (PREC == APEX_PREC_FP32 ? 4 : 2) : (NL == 1 ? 16 * H1 * M::EB : 0);
     const uint4* src = reinterpret_cast<const uint4*>(A.pd.wo);
     uint4* dst = reinterpret_cast<uint4*>(sWo);
-    for (int i = tid; i < wo_bytes / 16; i += kThreads) dst[i] = src[i];
+    for (int i = tid; i < wo_bytes / 16; i += T) dst[i] = src[i];
+    if (NL == 2)
+      for (int i = tid; i < (int)H2; i += T) sB2[i] = A.pd.b2[i];
   }
   const uint4* w2g = reinterpret_cast<const uint4*>(A.pd.w2);
 
@@ -226,6 +238,15 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
   }
 
   for (; v < vend; v += (GATHER ? vend : 1)) {
+    uint4 pre[NPRE];
+    // first GEMM weight chunk: loads issued now, stored after the activation phase
+    if (NL == 2) {
+#pragma unroll
+      for (int q = 0; q < NPRE; ++q) {
+        const int i = tid + q * T;
+        if (i < CHUNK / 16) pre[q] = w2g[i];
+      }
+    }
     // ---------------- locate the tile and stage its rows ----------------
     uint32_t a0 = 0, b0 = 0;
     if (!GATHER) {
@@ -240,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
       a0 = ta * TA;
       b0 = tb * TB;
       constexpr int V4 = H1 / 4;
-      for (int idx = tid; idx < (TA + TB) * V4; idx += kThreads) {
+      for (int idx = tid; idx < (TA + TB) * V4; idx += T) {
         const int row = idx / V4, c4 = idx - row * V4;
         float4 val;
         if (row < TA) {
@@ -262,12 +283,8 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
           *reinterpret_cast<float4*>(sB + (row - TA) * ROW + 4 * c4) = val;
         }
       }
+      __syncthreads();
     }
-    if (NL == 2) {  // first GEMM weight chunk
-      uint4* dst = reinterpret_cast<uint4*>(sW);
-      for (int i = tid; i < CHUNK / 16; i += kThreads) dst[i] = w2g[i];
-    }
-    __syncthreads();
 
     // ---------------- layer-1 activations into registers ----------------
     Frag X[R][NS];
@@ -277,10 +294,9 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
       const float* pa1 = nullptr;
       const float* pb;
       if (!GATHER) {
-        const int beta = wave * R + r;
-        const int aL = beta / NB, bL = (beta % NB) * 16 + j;
+        const int aL = wave * R + r;
         pa = sA + aL * ROW + g * KG;
-        pb = sB + bL * ROW + g * KG;
+        pb = sB + j * ROW + g * KG;
       } else {
         uint64_t item = v + (uint64_t)(wave * R + r) * 16 + j;
         item = item < A.n_ids ? item : (uint64_t)A.n_ids - 1;
@@ -341,7 +357,16 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
 #pragma unroll
     for (int r = 0; r < R; ++r) hacc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    if constexpr (NL == 1) {
+    if constexpr (NL == 0) {
+      // One-layer decoder (the paper's linear probe, eq. "apex"): the hoisted rows
+      // are the per-synthon head contributions (bias on slot 0), so their sum is
+      // the heads; lane group g holds heads 4 g .. 4 g + 3.
+      static_assert(PREC == APEX_PREC_FP32 && H1 == 16, "linear decoder: FP32, 16 padded heads");
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hacc[r][q] = X[r][q];
+    } else if constexpr (NL == 1) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const Frag wo = load_frag<PREC>(sWo + (size_t)(s * 64 + lane) * E * M::EB);
@@ -349,18 +374,32 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
         for (int r = 0; r < R; ++r) hacc[r] = M::mma(wo, X[r][s], hacc[r]);
       }
     } else {
-      uint32_t tprev[R][2];  // even chunk of a pair, already packed as bf16
-      for (int c = 0; c < NC; ++c) {
-        uint4 pre[NPRE];
+      // The staged rows are no longer needed: the region takes the weight chunks.
+      __syncthreads();
+      {
+        uint4* dst = reinterpret_cast<uint4*>(sW);
+#pragma unroll
+        for (int q = 0; q < NPRE; ++q) {
+          const int i = tid + q * T;
+          if (i < CHUNK / 16) dst[i] = pre[q];
+        }
+      }
+      __syncthreads();
+
+      // One chunk of 16 neurons: prefetch the next chunk, run the GEMM steps into
+      // `acc`, and meanwhile finish the previous chunk (activation and its share
+      // of the final layer) from `prev`; the two are independent, so the
+      // activation's VALU work overlaps the MFMAs.
+      uint32_t tprev[R][2];  // even chunk of a pair, packed bf16 (bf16/fp8 final layer)
+      auto gemm = [&](int c, f32x4 (&acc)[R]) {
         if (c + 1 < NC) {
 #pragma unroll
           for (int q = 0; q < NPRE; ++q) {
-            const int i = tid + q * kThreads;
+            const int i = tid + q * T;
             if (i < CHUNK / 16) pre[q] = w2g[(size_t)(c + 1) * (CHUNK / 16) + i];
           }
         }
-        const f32x4 binit = *reinterpret_cast<const f32x4*>(A.pd.b2 + c * 16 + g * 4);
-        f32x4 acc[R];
+        const f32x4 binit = *reinterpret_cast<const f32x4*>(sB2 + c * 16 + g * 4);
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = binit;
         const unsigned char* wc = sW + (c & 1) * CHUNK;
@@ -370,6 +409,8 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = M::mma(a, X[r][s], acc[r]);
         }
+      };
+      auto finish = [&](int c, const f32x4 (&acc)[R], bool odd) {  // odd: c & 1, a constant at each call
         float tv[R][4];
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -389,7 +430,7 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
               hacc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(wo, tv[r][q], hacc[r], 0, 0, 0);
           }
         } else {
-          if ((c & 1) == 0) {
+          if (!odd) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
               tprev[r][0] = __builtin_bit_cast(uint32_t, bf16x2{(__bf16)tv[r][0], (__bf16)tv[r][1]});
@@ -407,16 +448,34 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
             }
           }
         }
+      };
+      auto publish = [&](int c) {  // prefetched chunk c + 1 -> its LDS buffer
         if (c + 1 < NC) {
           uint4* dst = reinterpret_cast<uint4*>(sW + ((c + 1) & 1) * CHUNK);
 #pragma unroll
           for (int q = 0; q < NPRE; ++q) {
-            const int i = tid + q * kThreads;
+            const int i = tid + q * T;
             if (i < CHUNK / 16) dst[i] = pre[q];
           }
         }
         __syncthreads();
+      };
+      f32x4 accA[R], accB[R];
+      gemm(0, accA);
+      publish(0);
+      int c = 1;
+      for (; c + 1 < NC; c += 2) {
+        gemm(c, accB);
+        finish(c - 1, accA, false);
+        publish(c);
+        gemm(c + 1, accA);
+        finish(c, accB, true);
+        publish(c + 1);
       }
+      gemm(c, accB);  // c == NC - 1 (NC is even)
+      finish(c - 1, accA, false);
+      finish(c, accB, true);
+      __syncthreads();  // the region is restaged by the next tile
     }
 
     // ---------------- heads, objective, bounds, filter ----------------
@@ -425,8 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_enum(EnumArgs A) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (!GATHER) {
-        const int beta = wave * R + r;
-        const uint32_t a = a0 + beta / NB, b = b0 + (beta % NB) * 16 + j;
+        const uint32_t a = a0 + wave * R + r, b = b0 + j;
         valid[r] = a < Rt.nA && b < Rt.nB;
         cid[r] = Rt.id_off + (uint64_t)a * Rt.nB + b;
       } else {

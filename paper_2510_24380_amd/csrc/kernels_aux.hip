@@ -14,8 +14,8 @@ namespace apex {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_hoist(const float* __restrict__ U, uint32_t d, uint64_t rows,
                                                const float* __restrict__ W1, const float* __restrict__ b1,
-                                               uint32_t h1, const uint8_t* __restrict__ is_slot0, float c,
-                                               float* __restrict__ P) {
+                                               uint32_t n_w, uint32_t h1, const uint8_t* __restrict__ is_slot0,
+                                               float c, float* __restrict__ P) {
   __shared__ float sU[16][65];
   __shared__ float sW[16][65];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_hoist(const float* __restrict__ U, uint
       const uint32_t k = k0 + kk;
       sU[kk][rr] = (r < rows && k < d) ? U[r * d + k] : 0.0f;
       const uint32_t n = n0 + rr;
-      sW[kk][rr] = (n < h1 && k < d) ? W1[(uint64_t)n * d + k] : 0.0f;
+      sW[kk][rr] = (n < n_w && k < d) ? W1[(uint64_t)n * d + k] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_hoist(const float* __restrict__ U, uint
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t n = n0 + tx * 4 + q;
-      if (n < h1) P[r * h1 + n] = c * (acc[i][q] + (s0 ? b1[n] : 0.0f));
+      if (n < h1) P[r * h1 + n] = c * (acc[i][q] + (s0 && n < n_w ? b1[n] : 0.0f));
     }
   }
 }
@@ -217,8 +217,12 @@ __device__ inline float objective16(const float* w, const float* h) {
   return canon_zero((p[0] + p[1]) + (p[2] + p[3]));
 }
 
+// Scores listed compounds for each query (objective, bounds, the query's reaction
+// subset, threshold) and appends the passing ones to its candidate buffer with
+// one atomic per wave.
 __global__ void k_score(const float* __restrict__ heads, const uint64_t* __restrict__ ids, uint32_t n,
-                        const QueryDev* __restrict__ qs, uint32_t nq) {
+                        const QueryDev* __restrict__ qs, uint32_t nq, const ReactDev* __restrict__ react,
+                        uint32_t n_react) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t q = blockIdx.y;
   if (q >= nq) return;
@@ -227,7 +231,11 @@ __global__ void k_score(const float* __restrict__ heads, const uint64_t* __restr
   bool pass = false;
   float o = 0.0f;
   uint64_t id = 0;
-  if (i < n) {
+  if (i < n && Q->subset_bits) {
+    const uint32_t t = find_reaction(react, n_react, ids[i]);
+    if (!((Q->subset_bits[t >> 5] >> (t & 31)) & 1u)) id = ~0ull;  // outside the query's reactions
+  }
+  if (i < n && id != ~0ull) {
     float h[kHeadsPad];
 #pragma unroll
     for (int k = 0; k < kHeadsPad; ++k) h[k] = heads[(uint64_t)i * kHeadsPad + k];
@@ -238,11 +246,20 @@ __global__ void k_score(const float* __restrict__ heads, const uint64_t* __restr
     id = ids[i];
     pass = ok && key_passes(o, id, Q->st->tau_o, Q->st->tau_id);
   }
-  if (pass) {
-    const uint32_t idx = atomicAdd(&Q->st->count, 1u);
-    if (idx < Q->cap) {
-      Q->cand_o[idx] = o;
-      Q->cand_id[idx] = id;
+  const uint64_t m = __ballot(pass);
+  if (m) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    const uint32_t first = (uint32_t)__ffsll((long long)m) - 1;
+    if (lane == first) base = atomicAdd(&Q->st->count, (uint32_t)__popcll(m));
+    base = __shfl(base, (int)first);
+    if (pass) {
+      const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+      const uint32_t idx = base + (uint32_t)__popcll(m & below);
+      if (idx < Q->cap) {
+        Q->cand_o[idx] = o;
+        Q->cand_id[idx] = id;
+      }
     }
   }
 }
@@ -492,10 +509,10 @@ __global__ void k_head_err(const float* __restrict__ h_lp, const float* __restri
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_hoist(const float* U, uint32_t d, uint64_t rows, const float* W1, const float* b1, uint32_t h1,
-                        const uint8_t* is_slot0, float c, float* P, hipStream_t s) {
+hipError_t launch_hoist(const float* U, uint32_t d, uint64_t rows, const float* W1, const float* b1, uint32_t n_w,
+                        uint32_t h1, const uint8_t* is_slot0, float c, float* P, hipStream_t s) {
   dim3 grid((unsigned)((rows + 63) / 64), (h1 + 63) / 64);
-  hipLaunchKernelGGL(k_hoist, grid, dim3(256), 0, s, U, d, rows, W1, b1, h1, is_slot0, c, P);
+  hipLaunchKernelGGL(k_hoist, grid, dim3(256), 0, s, U, d, rows, W1, b1, n_w, h1, is_slot0, c, P);
   return hipGetLastError();
 }
 
@@ -546,9 +563,9 @@ hipError_t launch_bias(const float* b2, uint32_t h2, float c, const float* scal,
 }
 
 hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,
-                        hipStream_t s) {
+                        const ReactDev* react, uint32_t n_react, hipStream_t s) {
   if (n == 0 || nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_score, dim3((n + 255) / 256, nq), dim3(256), 0, s, heads, ids, n, qs, nq);
+  hipLaunchKernelGGL(k_score, dim3((n + 255) / 256, nq), dim3(256), 0, s, heads, ids, n, qs, nq, react, n_react);
   return hipGetLastError();
 }
 

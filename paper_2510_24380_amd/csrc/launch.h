@@ -9,8 +9,8 @@ hipError_t launch_enum(int prec, int h1, int nl, int act, bool gather, const Enu
 int enum_rows_per_block_wave(int prec);  // R: blocks of 16 compounds per wave
 hipError_t enum_prepare(int prec, int h1, int nl, int act, bool gather, uint32_t h2, int* max_wg_per_cu);
 
-hipError_t launch_hoist(const float* U, uint32_t d, uint64_t rows, const float* W1, const float* b1, uint32_t h1,
-                        const uint8_t* is_slot0, float c, float* P, hipStream_t s);
+hipError_t launch_hoist(const float* U, uint32_t d, uint64_t rows, const float* W1, const float* b1, uint32_t n_w,
+                        uint32_t h1, const uint8_t* is_slot0, float c, float* P, hipStream_t s);
 hipError_t launch_act_range(const float* P, uint32_t h1, const uint64_t* slot_row0, const uint32_t* slot_size,
                             uint32_t n_slots_total, const uint32_t* react_slot0, const uint32_t* react_nslots,
                             uint32_t n_react, int act, float c, float* cmax, float* cmin, float* out,
@@ -24,7 +24,7 @@ hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, int bf16,
 hipError_t launch_bias(const float* b2, uint32_t h2, float c, const float* scal, const float* bo, uint32_t H,
                        float* b2_out, float* bo_out, hipStream_t s);
 hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,
-                        hipStream_t s);
+                        const ReactDev* react, uint32_t n_react, hipStream_t s);
 hipError_t launch_select(const QueryDev* qs, uint32_t nq, uint32_t chunk_id, int force, hipStream_t s);
 hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s);
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,

@@ -22,8 +22,8 @@
 #include <limits>
 #include <vector>
 
-#include "engine_impl.h"
 #include "launch.h"
+#include "search_impl.h"
 
 using namespace apex;
 
@@ -34,52 +34,7 @@ using namespace apex;
       return set_error(APEX_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-namespace {
-
-struct Bump {
-  char* base;
-  size_t off = 0;
-  explicit Bump(void* b) : base((char*)b) {}
-  template <class T> T* take(size_t count) {
-    const size_t o = off;
-    off = (off + count * sizeof(T) + 255) & ~(size_t)255;
-    return base ? reinterpret_cast<T*>(base + o) : nullptr;
-  }
-};
-
-struct QPlan {
-  uint32_t k = 0, K = 0, cap = 0, hwm = 0, cap2 = 0;
-  bool lowp = false;
-  QState* st = nullptr;
-  float* cand_o = nullptr;
-  uint64_t* cand_id = nullptr;
-  float* tmp_o = nullptr;
-  uint64_t* tmp_id = nullptr;
-  uint32_t* rerun = nullptr;
-  uint32_t* subset_dev = nullptr;
-  float* pool_heads = nullptr;
-  QState* st2 = nullptr;
-  float* cand2_o = nullptr;
-  uint64_t* cand2_id = nullptr;
-  float* tmp2_o = nullptr;
-  uint64_t* tmp2_id = nullptr;
-  float* fin_o = nullptr;
-  uint64_t* fin_id = nullptr;
-  float* fin_heads = nullptr;
-  uint32_t* fin_reaction = nullptr;
-  uint32_t* fin_synthon = nullptr;
-};
-
-struct Shared {
-  QueryDev* qd = nullptr;   // enumeration-pass queries (relaxed bounds in low precision)
-  QueryDev* qx = nullptr;   // exact-bound queries of the rescoring pass
-  SelDev* plan = nullptr;
-  uint64_t* sample_ids = nullptr;
-  float* sample_heads = nullptr;
-  uint32_t* fill_zero = nullptr;
-  uint32_t n_sample = 0;
-  uint32_t max_chunks = 0;
-};
+namespace apex {
 
 constexpr uint64_t kFirstChunk = 1ull << 22;  // compounds in the first chunk
 constexpr uint64_t kMaxChunk = 1ull << 27;
@@ -108,7 +63,7 @@ std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint
 
 uint32_t tile_compounds(int prec) { return (uint32_t)(tile_ta(prec) * tile_tb(prec)); }
 
-apex_status validate(const apex_engine* E, const apex_query* q) {
+apex_status validate_query(const apex_engine* E, const apex_query* q) {
   if (!q) return set_error(APEX_E_INVALID, "null query");
   if (!q->objective_w) return set_error(APEX_E_INVALID, "null objective_w");
   if (q->k == 0) return set_error(APEX_E_INVALID, "k must be >= 1");
@@ -142,10 +97,6 @@ apex_status validate(const apex_engine* E, const apex_query* q) {
   return APEX_OK;
 }
 
-uint32_t max_chunks(const apex_engine* E, int prec) {
-  return (uint32_t)chunk_schedule(E->prec[prec].full_tiles, tile_compounds(prec)).size() + 1;
-}
-
 void query_sizes(const apex_query* q, QPlan& P) {
   P.k = (uint32_t)q->k;
   P.lowp = q->precision != APEX_PREC_FP32;
@@ -160,56 +111,40 @@ void query_sizes(const apex_query* q, QPlan& P) {
   P.cap2 = P.K;
 }
 
-uint32_t sample_count(const std::vector<QPlan>& P) {
-  uint32_t kmax = 0, capmin = UINT32_MAX;
-  for (auto& p : P) {
-    kmax = std::max(kmax, p.K);
-    capmin = std::min(capmin, p.cap);
+void query_layout(uint32_t T, uint32_t n_flags, Bump& b, QPlan& p) {
+  p.n_flags = n_flags;
+  p.st = b.take<QState>(1);
+  p.cand_o = b.take<float>(p.cap);
+  p.cand_id = b.take<uint64_t>(p.cap);
+  p.tmp_o = b.take<float>(p.K);
+  p.tmp_id = b.take<uint64_t>(p.K);
+  p.rerun = b.take<uint32_t>(n_flags);
+  p.subset_dev = b.take<uint32_t>((T + 31) / 32);
+  if (p.lowp) {
+    p.pool_heads = b.take<float>((size_t)p.K * kHeadsPad);
+    p.st2 = b.take<QState>(1);
+    p.cand2_o = b.take<float>(p.cap2);
+    p.cand2_id = b.take<uint64_t>(p.cap2);
+    p.tmp2_o = b.take<float>(p.k);
+    p.tmp2_id = b.take<uint64_t>(p.k);
   }
-  uint64_t s = std::min<uint64_t>(std::max<uint64_t>(32ull * kmax, 1ull << 16), 1ull << 20);
-  return (uint32_t)std::min<uint64_t>(s, capmin);
-}
-
-void layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& b, std::vector<QPlan>& P, Shared& sh) {
-  P.assign(n, QPlan());
-  for (uint32_t i = 0; i < n; ++i) query_sizes(&qs[i], P[i]);
-  const int prec = (int)qs[0].precision;
-  sh.max_chunks = max_chunks(E, prec);
-  sh.n_sample = sample_count(P);
-  const uint32_t T = E->lib->T;
-  sh.qd = b.take<QueryDev>(n);
-  sh.qx = b.take<QueryDev>(n);
-  sh.plan = b.take<SelDev>(T);
-  sh.sample_ids = b.take<uint64_t>(sh.n_sample);
-  sh.sample_heads = b.take<float>((size_t)sh.n_sample * kHeadsPad);
-  for (uint32_t i = 0; i < n; ++i) {
-    QPlan& p = P[i];
-    p.st = b.take<QState>(1);
-    p.cand_o = b.take<float>(p.cap);
-    p.cand_id = b.take<uint64_t>(p.cap);
-    p.tmp_o = b.take<float>(p.K);
-    p.tmp_id = b.take<uint64_t>(p.K);
-    p.rerun = b.take<uint32_t>(sh.max_chunks + 1);
-    p.subset_dev = b.take<uint32_t>((T + 31) / 32);
-    if (p.lowp) {
-      p.pool_heads = b.take<float>((size_t)p.K * kHeadsPad);
-      p.st2 = b.take<QState>(1);
-      p.cand2_o = b.take<float>(p.cap2);
-      p.cand2_id = b.take<uint64_t>(p.cap2);
-      p.tmp2_o = b.take<float>(p.k);
-      p.tmp2_id = b.take<uint64_t>(p.k);
-    }
-    p.fin_o = b.take<float>(p.k);
-    p.fin_id = b.take<uint64_t>(p.k);
-    p.fin_heads = b.take<float>((size_t)p.k * kHeadsPad);
-    p.fin_reaction = b.take<uint32_t>(p.k);
-    p.fin_synthon = b.take<uint32_t>((size_t)p.k * 3);
-  }
+  p.fin_o = b.take<float>(p.k);
+  p.fin_id = b.take<uint64_t>(p.k);
+  p.fin_heads = b.take<float>((size_t)p.k * kHeadsPad);
+  p.fin_reaction = b.take<uint32_t>(p.k);
+  p.fin_synthon = b.take<uint32_t>((size_t)p.k * 3);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+apex_status fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return APEX_OK;
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  HIP_TRY(hipGetLastError());
+  return APEX_OK;
 }
 
 QueryDev make_qdev(const apex_engine* E, const apex_query* q, const QPlan& p, bool relaxed, bool stage2) {
@@ -247,7 +182,7 @@ QueryDev make_qdev(const apex_engine* E, const apex_query* q, const QPlan& p, bo
     d.cand_id = p.cand2_id;
     d.tmp_o = p.tmp2_o;
     d.tmp_id = p.tmp2_id;
-    d.rerun = p.rerun;  // not used: stage 2 never overflows (cap2 >= pool)
+    d.rerun = p.rerun;  // never flagged: the rescoring buffer holds the whole pool
     d.cap = p.cap2;
     d.K = p.k;
     d.hwm = p.cap2;
@@ -257,21 +192,202 @@ QueryDev make_qdev(const apex_engine* E, const apex_query* q, const QPlan& p, bo
   return d;
 }
 
-struct EventPool {
-  std::vector<hipEvent_t> ev;
-  size_t used = 0;
-  hipEvent_t get() {
-    if (used == ev.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      ev.push_back(e);
+std::vector<uint32_t> subset_bits(const apex_engine* E, const apex_query* q) {
+  std::vector<uint32_t> bits;
+  if (q->n_subset) {
+    bits.assign((E->lib->T + 31) / 32, 0u);
+    for (uint32_t j = 0; j < q->n_subset; ++j) bits[q->subset[j] >> 5] |= 1u << (q->subset[j] & 31);
+  }
+  return bits;
+}
+
+apex_status query_device_init(const apex_engine* E, const apex_query* q, const QPlan& P, hipStream_t s) {
+  QState init{};
+  init.tau_o = -INFINITY;
+  init.tau_id = ~0ull;
+  HIP_TRY(hipMemcpyAsync(P.st, &init, sizeof(QState), hipMemcpyHostToDevice, s));
+  if (P.lowp) HIP_TRY(hipMemcpyAsync(P.st2, &init, sizeof(QState), hipMemcpyHostToDevice, s));
+  const std::vector<uint32_t> bits = subset_bits(E, q);
+  if (!bits.empty())
+    HIP_TRY(hipMemcpyAsync(P.subset_dev, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, s));
+  return fill_u32(P.rerun, P.n_flags, 0u, s);
+}
+
+uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev>& plan, uint64_t v0, uint64_t v1) {
+  uint64_t c = 0;
+  const uint64_t TA = tile_ta(prec), TB = tile_tb(prec);
+  for (size_t r = 0; r < plan.size(); ++r) {
+    const ReactDev& rd = E->react_host[plan[r].t];
+    const uint64_t ta = (rd.nA + TA - 1) / TA;
+    const uint64_t t0 = plan[r].tile_start, t1 = t0 + ta * plan[r].tiles_b;
+    if (t1 <= v0 || t0 >= v1) continue;
+    if (t0 >= v0 && t1 <= v1) {
+      c += (uint64_t)rd.nA * rd.nB;
+      continue;
     }
-    return ev[used++];
+    // partially covered reaction: count tile by tile, ragged edges included
+    for (uint64_t v = std::max(v0, t0); v < std::min(v1, t1); ++v) {
+      const uint64_t lt = v - t0;
+      const uint64_t ia = lt / plan[r].tiles_b, ib = lt % plan[r].tiles_b;
+      c += std::min<uint64_t>(TA, rd.nA - ia * TA) * std::min<uint64_t>(TB, rd.nB - ib * TB);
+    }
   }
-  ~EventPool() {
-    for (auto e : ev) (void)hipEventDestroy(e);
+  return c;
+}
+
+apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t v0, uint64_t v1,
+                      const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, hipStream_t s) {
+  const PrecState& PS = E->prec[prec];
+  EnumArgs a{};
+  a.P = E->P;
+  a.react = E->react;
+  a.sel = plan_dev;
+  a.n_sel = n_sel;
+  a.pd = PS.dev;
+  a.H2 = E->H2;
+  a.n_queries = nq;
+  a.queries = qd_dev;
+  a.n_reactions = E->lib->T;
+  a.n_total = E->lib->total;
+  a.tile_begin = v0;
+  a.tile_end = v1;
+  uint32_t grid_full = (uint32_t)(E->n_cu * PS.wg_per_cu);
+  grid_full = std::max<uint32_t>(8, grid_full / 8 * 8);
+  const uint64_t nt = v1 - v0;
+  const uint32_t grid = nt < grid_full ? (uint32_t)nt : grid_full;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (E->profile) {
+    for (hipEvent_t* e : {&e0, &e1}) {
+      if (!E->ev_free.empty()) {
+        *e = E->ev_free.back();
+        E->ev_free.pop_back();
+      } else {
+        HIP_TRY(hipEventCreate(e));
+      }
+    }
+    HIP_TRY(hipEventRecord(e0, s));
   }
+  HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, false, a, grid, s));
+  if (E->profile) {
+    HIP_TRY(hipEventRecord(e1, s));
+    E->ev_pending.push_back({e0, e1, compounds});
+  }
+  return APEX_OK;
+}
+
+apex_status profile_collect(apex_engine* E) {
+  for (auto& t : E->ev_pending) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventSynchronize(t.b));
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    E->prof_ms += ms;
+    E->prof_launches += 1;
+    E->prof_compounds += t.compounds;
+    E->ev_free.push_back(t.a);
+    E->ev_free.push_back(t.b);
+  }
+  E->ev_pending.clear();
+  return APEX_OK;
+}
+
+apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_comp,
+                       uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev, uint32_t nq,
+                       hipStream_t s) {
+  HIP_TRY(launch_sample_ids(plan_dev, n_sel, E->react, n_comp, n_sample, 0xa5e7c0de1234ull, ids, s));
+  apex_status st = engine_gather(E, prec, ids, n_sample, heads, s);
+  if (st != APEX_OK) return st;
+  HIP_TRY(launch_score(heads, ids, n_sample, qd_dev, nq, E->react, E->lib->T, s));
+  HIP_TRY(launch_select(qd_dev, nq, 0, 1, s));
+  HIP_TRY(launch_tau_relax(qd_dev, nq, s));
+  return APEX_OK;
+}
+
+apex_status finish_query(apex_engine* E, const apex_query* q, const QPlan& P, const QueryDev* qd_dev,
+                         const QueryDev* qx_dev, hipStream_t s, apex_result* res) {
+  (void)q;
+  QState st1{}, st2{};
+  HIP_TRY(hipMemcpyAsync(&st1, P.st, sizeof(QState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const uint32_t n1 = std::min(st1.count, P.K);
+  uint32_t n_found = 0;
+  if (!P.lowp) {
+    HIP_TRY(launch_rank_sort(qd_dev, 0, P.K, P.fin_o, P.fin_id, s));
+    n_found = n1;
+  } else if (n1 > 0) {
+    apex_status st = engine_gather(E, APEX_PREC_FP32, P.cand_id, n1, P.pool_heads, s);
+    if (st != APEX_OK) return st;
+    HIP_TRY(launch_score(P.pool_heads, P.cand_id, n1, qx_dev, 1, E->react, E->lib->T, s));
+    HIP_TRY(launch_select(qx_dev, 1, 0, 1, s));
+    HIP_TRY(launch_rank_sort(qx_dev, 0, P.k, P.fin_o, P.fin_id, s));
+    HIP_TRY(hipMemcpyAsync(&st2, P.st2, sizeof(QState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    n_found = std::min(st2.count, P.k);
+  }
+  res->n_found = n_found;
+  res->n_candidates = st1.appended;
+  if (n_found == 0) return APEX_OK;
+  std::vector<float> heads;
+  apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, n_found, P.fin_heads, s);
+  if (st != APEX_OK) return st;
+  HIP_TRY(launch_decode(E->react, E->lib->T, P.fin_id, P.lowp ? P.st2 : P.st, P.k, P.fin_reaction, P.fin_synthon,
+                        s));
+  HIP_TRY(hipMemcpyAsync(res->ids, P.fin_id, sizeof(uint64_t) * n_found, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(res->objective, P.fin_o, sizeof(float) * n_found, hipMemcpyDeviceToHost, s));
+  if (res->heads) {
+    heads.resize((size_t)n_found * kHeadsPad);
+    HIP_TRY(hipMemcpyAsync(heads.data(), P.fin_heads, sizeof(float) * n_found * kHeadsPad, hipMemcpyDeviceToHost,
+                           s));
+  }
+  if (res->reaction)
+    HIP_TRY(hipMemcpyAsync(res->reaction, P.fin_reaction, sizeof(uint32_t) * n_found, hipMemcpyDeviceToHost, s));
+  if (res->synthon)
+    HIP_TRY(hipMemcpyAsync(res->synthon, P.fin_synthon, sizeof(uint32_t) * 3 * n_found, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (res->heads)
+    for (uint32_t e = 0; e < n_found; ++e)
+      std::memcpy(res->heads + (size_t)e * E->H, heads.data() + (size_t)e * kHeadsPad, sizeof(float) * E->H);
+  return APEX_OK;
+}
+
+}  // namespace apex
+
+namespace {
+
+struct Shared {
+  QueryDev* qd = nullptr;   // enumeration-pass queries (relaxed bounds in low precision)
+  QueryDev* qx = nullptr;   // exact-bound queries of the rescoring pass
+  SelDev* plan = nullptr;
+  uint64_t* sample_ids = nullptr;
+  float* sample_heads = nullptr;
+  uint32_t n_sample = 0;
+  uint32_t n_flags = 0;
 };
+
+uint32_t sample_count(const std::vector<QPlan>& P) {
+  uint32_t kmax = 0, capmin = UINT32_MAX;
+  for (auto& p : P) {
+    kmax = std::max(kmax, p.K);
+    capmin = std::min(capmin, p.cap);
+  }
+  uint64_t s = std::min<uint64_t>(std::max<uint64_t>(32ull * kmax, 1ull << 16), 1ull << 20);
+  return (uint32_t)std::min<uint64_t>(s, capmin);
+}
+
+void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& b, std::vector<QPlan>& P,
+                  Shared& sh) {
+  P.assign(n, QPlan());
+  for (uint32_t i = 0; i < n; ++i) query_sizes(&qs[i], P[i]);
+  const int prec = (int)qs[0].precision;
+  sh.n_flags = (uint32_t)chunk_schedule(E->prec[prec].full_tiles, tile_compounds(prec)).size() + 1;
+  sh.n_sample = sample_count(P);
+  const uint32_t T = E->lib->T;
+  sh.qd = b.take<QueryDev>(n);
+  sh.qx = b.take<QueryDev>(n);
+  sh.plan = b.take<SelDev>(T);
+  sh.sample_ids = b.take<uint64_t>(sh.n_sample);
+  sh.sample_heads = b.take<float>((size_t)sh.n_sample * kHeadsPad);
+  for (uint32_t i = 0; i < n; ++i) query_layout(T, sh.n_flags, b, P[i]);
+}
 
 }  // namespace
 
@@ -280,7 +396,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   if (!E || !qs || !res || nq == 0) return set_error(APEX_E_INVALID, "null argument");
   if (nq > APEX_MAX_FUSED_QUERIES) return set_error(APEX_E_INVALID, "%u queries > %d", nq, APEX_MAX_FUSED_QUERIES);
   for (uint32_t i = 0; i < nq; ++i) {
-    apex_status st = validate(E, &qs[i]);
+    apex_status st = validate_query(E, &qs[i]);
     if (st != APEX_OK) return st;
     if (qs[i].precision != qs[0].precision)
       return set_error(APEX_E_INVALID, "fused queries must share one precision");
@@ -291,33 +407,23 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   if (((uintptr_t)ws) & 255) return set_error(APEX_E_INVALID, "workspace must be 256-byte aligned");
   const int prec = (int)qs[0].precision;
   const apex_library* L = E->lib;
-  PrecState& PS = E->prec[prec];
 
   std::vector<QPlan> P;
   Shared sh;
   {
     Bump b(nullptr);
-    layout(E, qs, nq, b, P, sh);
+    batch_layout(E, qs, nq, b, P, sh);
     if (b.off > ws_bytes)
       return set_error(APEX_E_NOMEM, "query workspace %zu bytes < %zu needed", ws_bytes, b.off);
   }
   Bump b(ws);
-  layout(E, qs, nq, b, P, sh);
+  batch_layout(E, qs, nq, b, P, sh);
 
   // reactions searched by at least one query
   std::vector<uint8_t> want(L->T, 0);
-  std::vector<std::vector<uint32_t>> bits(nq);
   for (uint32_t i = 0; i < nq; ++i) {
-    if (qs[i].n_subset == 0) {
-      std::fill(want.begin(), want.end(), 1);
-    } else {
-      bits[i].assign((L->T + 31) / 32, 0u);
-      for (uint32_t j = 0; j < qs[i].n_subset; ++j) {
-        const uint32_t t = qs[i].subset[j];
-        want[t] = 1;
-        bits[i][t >> 5] |= 1u << (t & 31);
-      }
-    }
+    if (qs[i].n_subset == 0) std::fill(want.begin(), want.end(), 1);
+    for (uint32_t j = 0; j < qs[i].n_subset; ++j) want[qs[i].subset[j]] = 1;
   }
   std::vector<uint32_t> reactions;
   for (uint32_t t = 0; t < L->T; ++t)
@@ -326,204 +432,85 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   uint64_t n_tiles = 0, n_comp = 0;
   build_plan(L, prec, reactions, plan, &n_tiles, &n_comp);
 
-  // device state
   std::vector<QueryDev> qd(nq), qx(nq);
   for (uint32_t i = 0; i < nq; ++i) {
+    apex_status st = query_device_init(E, &qs[i], P[i], s);
+    if (st != APEX_OK) return st;
     qd[i] = make_qdev(E, &qs[i], P[i], true, false);
     qx[i] = make_qdev(E, &qs[i], P[i], false, P[i].lowp);
   }
-  QState init{};
-  init.tau_o = -INFINITY;
-  init.tau_id = ~0ull;
-  for (uint32_t i = 0; i < nq; ++i) {
-    HIP_TRY(hipMemcpyAsync(P[i].st, &init, sizeof(QState), hipMemcpyHostToDevice, s));
-    if (P[i].lowp) HIP_TRY(hipMemcpyAsync(P[i].st2, &init, sizeof(QState), hipMemcpyHostToDevice, s));
-    if (!bits[i].empty())
-      HIP_TRY(hipMemcpyAsync(P[i].subset_dev, bits[i].data(), bits[i].size() * 4, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_u32, dim3((sh.max_chunks + 1 + 255) / 256), dim3(256), 0, s, P[i].rerun,
-                       sh.max_chunks + 1, 0u);
-  }
   HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(sh.qx, qx.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
-  if (!plan.empty()) HIP_TRY(hipMemcpyAsync(sh.plan, plan.data(), sizeof(SelDev) * plan.size(), hipMemcpyHostToDevice, s));
-
-  EnumArgs a{};
-  a.P = E->P;
-  a.react = E->react;
-  a.sel = sh.plan;
-  a.n_sel = (uint32_t)plan.size();
-  a.pd = PS.dev;
-  a.H2 = E->H2;
-  a.n_queries = nq;
-  a.queries = sh.qd;
-  a.n_reactions = L->T;
+  if (!plan.empty())
+    HIP_TRY(hipMemcpyAsync(sh.plan, plan.data(), sizeof(SelDev) * plan.size(), hipMemcpyHostToDevice, s));
 
   uint64_t scored = 0;
-  // 1. threshold warm start from a stratified sample
+  // 1. threshold warm start from a stratified sample of the searched reactions
   if (n_comp >= 8ull * sh.n_sample) {
-    HIP_TRY(launch_sample_ids(sh.plan, (uint32_t)plan.size(), E->react, n_comp, sh.n_sample, 0xa5e7c0de1234ull,
-                              sh.sample_ids, s));
-    apex_status st = engine_gather(E, prec, sh.sample_ids, sh.n_sample, sh.sample_heads, s);
+    apex_status st = warm_start(E, prec, sh.plan, (uint32_t)plan.size(), n_comp, sh.n_sample, sh.sample_ids,
+                                sh.sample_heads, sh.qd, nq, s);
     if (st != APEX_OK) return st;
-    HIP_TRY(launch_score(sh.sample_heads, sh.sample_ids, sh.n_sample, sh.qd, nq, s));
-    HIP_TRY(launch_select(sh.qd, nq, sh.max_chunks, 1, s));
-    HIP_TRY(launch_tau_relax(sh.qd, nq, s));
     scored += sh.n_sample;
   }
 
   // 2. chunked enumeration
   const auto chunks = chunk_schedule(n_tiles, tile_compounds(prec));
-  if (chunks.size() + 1 > sh.max_chunks + 1) return set_error(APEX_E_INVALID, "internal: chunk count");
-  uint32_t grid_full = (uint32_t)(E->n_cu * PS.wg_per_cu);
-  grid_full = std::max<uint32_t>(8, grid_full / 8 * 8);
-  EventPool evp;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
-  std::vector<uint64_t> timed_comp;
-  auto chunk_compounds = [&](uint64_t v0, uint64_t v1) -> uint64_t {
-    // compounds of the selection inside tiles [v0, v1) (ragged tiles counted exactly)
-    uint64_t c = 0;
-    for (size_t r = 0; r < plan.size(); ++r) {
-      const ReactDev& rd = E->react_host[plan[r].t];
-      const uint64_t ta = (rd.nA + tile_ta(prec) - 1) / tile_ta(prec);
-      const uint64_t t0 = plan[r].tile_start, t1 = t0 + ta * plan[r].tiles_b;
-      if (t1 <= v0 || t0 >= v1) continue;
-      if (t0 >= v0 && t1 <= v1) {
-        c += (uint64_t)rd.nA * rd.nB;
-        continue;
-      }
-      for (uint64_t v = std::max(v0, t0); v < std::min(v1, t1); ++v) {
-        const uint64_t lt = v - t0;
-        const uint64_t ia = lt / plan[r].tiles_b, ib = lt % plan[r].tiles_b;
-        const uint64_t na = std::min<uint64_t>(tile_ta(prec), rd.nA - ia * tile_ta(prec));
-        const uint64_t nb = std::min<uint64_t>(tile_tb(prec), rd.nB - ib * tile_tb(prec));
-        c += na * nb;
-      }
-    }
-    return c;
-  };
-  auto enum_chunk = [&](uint64_t v0, uint64_t v1) -> apex_status {
-    a.tile_begin = v0;
-    a.tile_end = v1;
-    const uint64_t nt = v1 - v0;
-    const uint32_t grid = nt < grid_full ? (uint32_t)nt : grid_full;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (E->profile) {
-      e0 = evp.get();
-      e1 = evp.get();
-      if (e0) HIP_TRY(hipEventRecord(e0, s));
-    }
-    HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, false, a, grid, s));
-    if (E->profile && e0 && e1) {
-      HIP_TRY(hipEventRecord(e1, s));
-      timed.emplace_back(e0, e1);
-      timed_comp.push_back(chunk_compounds(v0, v1));
-    }
-    return APEX_OK;
-  };
+  if (chunks.size() + 1 > sh.n_flags) return set_error(APEX_E_INVALID, "internal: chunk count");
+  const uint32_t last_flag = sh.n_flags - 1;  // flag slot of the closing selections (never set)
   for (size_t c = 0; c < chunks.size(); ++c) {
-    apex_status st = enum_chunk(chunks[c].first, chunks[c].second);
+    apex_status st = enum_pass(E, prec, sh.plan, (uint32_t)plan.size(), chunks[c].first, chunks[c].second, sh.qd,
+                               nq, plan_compounds(E, prec, plan, chunks[c].first, chunks[c].second), s);
     if (st != APEX_OK) return st;
     HIP_TRY(launch_select(sh.qd, nq, (uint32_t)c, 0, s));
   }
   scored += n_comp;
-  HIP_TRY(launch_select(sh.qd, nq, sh.max_chunks, 1, s));
+  HIP_TRY(launch_select(sh.qd, nq, last_flag, 1, s));
 
   // re-runs of chunks whose appends overflowed a candidate buffer
-  std::vector<uint32_t> flags((size_t)nq * (sh.max_chunks + 1));
+  std::vector<uint32_t> flags((size_t)nq * sh.n_flags);
   uint32_t reruns = 0;
   for (int round = 0;; ++round) {
     for (uint32_t i = 0; i < nq; ++i)
-      HIP_TRY(hipMemcpyAsync(flags.data() + (size_t)i * (sh.max_chunks + 1), P[i].rerun,
-                             sizeof(uint32_t) * (sh.max_chunks + 1), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(flags.data() + (size_t)i * sh.n_flags, P[i].rerun, sizeof(uint32_t) * sh.n_flags,
+                             hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     bool any = false;
     for (uint32_t f : flags) any |= f != 0;
     if (!any) break;
     if (round > 64) return set_error(APEX_E_DEVICE, "candidate buffer overflow did not settle");
-    for (uint32_t i = 0; i < nq; ++i)
-      hipLaunchKernelGGL(k_fill_u32, dim3((sh.max_chunks + 1 + 255) / 256), dim3(256), 0, s, P[i].rerun,
-                         sh.max_chunks + 1, 0u);
+    for (uint32_t i = 0; i < nq; ++i) {
+      apex_status st = fill_u32(P[i].rerun, sh.n_flags, 0u, s);
+      if (st != APEX_OK) return st;
+    }
     for (size_t c = 0; c < chunks.size(); ++c) {
       bool need = false;
       for (uint32_t i = 0; i < nq; ++i) {
-        qd[i].active = flags[(size_t)i * (sh.max_chunks + 1) + c] ? 1u : 0u;
+        qd[i].active = flags[(size_t)i * sh.n_flags + c] ? 1u : 0u;
         need |= qd[i].active != 0;
       }
       if (!need) continue;
       HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
-      apex_status st = enum_chunk(chunks[c].first, chunks[c].second);
+      const uint64_t cc = plan_compounds(E, prec, plan, chunks[c].first, chunks[c].second);
+      apex_status st = enum_pass(E, prec, sh.plan, (uint32_t)plan.size(), chunks[c].first, chunks[c].second,
+                                 sh.qd, nq, cc, s);
       if (st != APEX_OK) return st;
       HIP_TRY(launch_select(sh.qd, nq, (uint32_t)c, 0, s));
-      scored += chunk_compounds(chunks[c].first, chunks[c].second);
+      scored += cc;
       ++reruns;
     }
     for (uint32_t i = 0; i < nq; ++i) qd[i].active = 1;
     HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_select(sh.qd, nq, sh.max_chunks, 1, s));
+    HIP_TRY(launch_select(sh.qd, nq, last_flag, 1, s));
   }
 
   // 3-4. answer of each query
-  std::vector<QState> stv(nq), st2v(nq);
-  for (uint32_t i = 0; i < nq; ++i)
-    HIP_TRY(hipMemcpyAsync(&stv[i], P[i].st, sizeof(QState), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  std::vector<uint32_t> n_found(nq);
   for (uint32_t i = 0; i < nq; ++i) {
-    const uint32_t n1 = std::min(stv[i].count, P[i].K);
-    if (!P[i].lowp) {
-      HIP_TRY(launch_rank_sort(sh.qd, i, P[i].K, P[i].fin_o, P[i].fin_id, s));
-      n_found[i] = n1;
-    } else if (n1 > 0) {
-      apex_status st = engine_gather(E, APEX_PREC_FP32, P[i].cand_id, n1, P[i].pool_heads, s);
-      if (st != APEX_OK) return st;
-      HIP_TRY(launch_score(P[i].pool_heads, P[i].cand_id, n1, sh.qx + i, 1, s));
-      HIP_TRY(launch_select(sh.qx + i, 1, 0, 1, s));
-      HIP_TRY(launch_rank_sort(sh.qx, i, P[i].k, P[i].fin_o, P[i].fin_id, s));
-      HIP_TRY(hipMemcpyAsync(&st2v[i], P[i].st2, sizeof(QState), hipMemcpyDeviceToHost, s));
-    }
-  }
-  HIP_TRY(hipStreamSynchronize(s));
-  for (uint32_t i = 0; i < nq; ++i) {
-    if (P[i].lowp) n_found[i] = std::min(st2v[i].count, P[i].k);
-    if (n_found[i] == 0) continue;
-    apex_status st = engine_gather(E, APEX_PREC_FP32, P[i].fin_id, n_found[i], P[i].fin_heads, s);
+    apex_status st = finish_query(E, &qs[i], P[i], sh.qd + i, sh.qx + i, s, &res[i]);
     if (st != APEX_OK) return st;
-    HIP_TRY(launch_decode(E->react, L->T, P[i].fin_id, P[i].lowp ? P[i].st2 : P[i].st, P[i].k, P[i].fin_reaction,
-                          P[i].fin_synthon, s));
+    res[i].n_scored = scored;
+    res[i].n_reruns = reruns;
   }
-  std::vector<std::vector<float>> heads(nq);
-  for (uint32_t i = 0; i < nq; ++i) {
-    const uint32_t n = n_found[i];
-    apex_result& r = res[i];
-    r.n_found = n;
-    r.n_scored = scored;
-    r.n_candidates = stv[i].appended;
-    r.n_reruns = reruns;
-    if (n == 0) continue;
-    HIP_TRY(hipMemcpyAsync(r.ids, P[i].fin_id, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(r.objective, P[i].fin_o, sizeof(float) * n, hipMemcpyDeviceToHost, s));
-    if (r.heads) {
-      heads[i].resize((size_t)n * kHeadsPad);
-      HIP_TRY(hipMemcpyAsync(heads[i].data(), P[i].fin_heads, sizeof(float) * n * kHeadsPad, hipMemcpyDeviceToHost, s));
-    }
-    if (r.reaction) HIP_TRY(hipMemcpyAsync(r.reaction, P[i].fin_reaction, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s));
-    if (r.synthon) HIP_TRY(hipMemcpyAsync(r.synthon, P[i].fin_synthon, sizeof(uint32_t) * 3 * n, hipMemcpyDeviceToHost, s));
-  }
-  HIP_TRY(hipStreamSynchronize(s));
-  for (uint32_t i = 0; i < nq; ++i)
-    if (res[i].heads && n_found[i])
-      for (uint32_t e = 0; e < n_found[i]; ++e)
-        std::memcpy(res[i].heads + (size_t)e * E->H, heads[i].data() + (size_t)e * kHeadsPad, sizeof(float) * E->H);
-  if (E->profile) {
-    for (size_t t = 0; t < timed.size(); ++t) {
-      float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, timed[t].first, timed[t].second));
-      E->prof_ms += ms;
-      E->prof_launches += 1;
-      E->prof_compounds += timed_comp[t];
-    }
-  }
-  return APEX_OK;
+  return profile_collect(E);
 }
 
 extern "C" apex_status apex_query_workspace_size(const apex_engine* eng, const apex_query* q, size_t* bytes) {
@@ -535,14 +522,14 @@ extern "C" apex_status apex_batch_workspace_size(const apex_engine* eng, const a
   if (!eng || !qs || !bytes || n == 0) return set_error(APEX_E_INVALID, "null argument");
   if (n > APEX_MAX_FUSED_QUERIES) return set_error(APEX_E_INVALID, "%u queries > %d", n, APEX_MAX_FUSED_QUERIES);
   for (uint32_t i = 0; i < n; ++i) {
-    apex_status st = validate(eng, &qs[i]);
+    apex_status st = validate_query(eng, &qs[i]);
     if (st != APEX_OK) return st;
     if (qs[i].precision != qs[0].precision) return set_error(APEX_E_INVALID, "fused queries must share one precision");
   }
   std::vector<QPlan> P;
   Shared sh;
   Bump b(nullptr);
-  layout(eng, qs, n, b, P, sh);
+  batch_layout(eng, qs, n, b, P, sh);
   *bytes = b.off;
   return APEX_OK;
 }
@@ -560,6 +547,8 @@ extern "C" apex_status apex_search_batch(apex_engine* eng, const apex_query* qs,
 extern "C" apex_status apex_engine_profile(apex_engine* eng, int enable, double* ms, uint64_t* launches,
                                            uint64_t* compounds) {
   if (!eng) return set_error(APEX_E_INVALID, "null engine");
+  apex_status st = profile_collect(eng);
+  if (st != APEX_OK) return st;
   if (ms) *ms = eng->prof_ms;
   if (launches) *launches = eng->prof_launches;
   if (compounds) *compounds = eng->prof_compounds;

@@ -93,3 +93,5 @@ def test_decoder_validation():
     assert create([64, 128, 64, 5]) == 0
     assert create([64, 128, 40, 5]) == -4     # second hidden width not a multiple of 32
     assert create([64, 0, 5]) == -1
+    assert create([64, 28]) == -4            # linear probe wider than one MFMA tile
+    assert create([64, 5]) == 0              # linear probe (one layer)

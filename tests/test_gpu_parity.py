@@ -208,3 +208,24 @@ def test_ids_beyond_32_bits():
     r = eng.search(q, precision="fp32")
     assert r.ids.min() >= 70000 * 70000 > 2 ** 32
     check_fp32_exact(lib_h, dec_h, q, r, "64-bit ids")
+
+
+@pytest.mark.parametrize("shape", [([2, 3, 2, 3], [37, 53, 11, 9, 17, 70, 3, 5, 4, 29], 256, 15),
+                                   ([2], [300, 300], 64, 5)])
+def test_linear_probe_decoder_exact(shape):
+    """One-layer decoder, the paper's linear heads (eq. "apex"): FP32 exact."""
+    from workloads.gen import ACT_NONE
+    n_slots, sizes, d, H = shape
+    print(f"case: linear probe d={d} H={H}", flush=True)
+    lib_h = g.make_library(59, n_slots, sizes, d)
+    dec_h = g.make_decoder(59, [d, H], ACT_NONE)
+    lib, dec, eng = device_objects(lib_h, dec_h, precisions=("fp32",))
+    sample = oracle.heads(lib_h, dec_h, np.arange(0, lib_h.n_compounds, 3, dtype=np.uint64))
+    w = np.zeros(H, np.float32)
+    w[0], w[H - 1] = 1.0, -0.5
+    cons = [Constraint(1, -math.inf, float(np.float32(np.quantile(sample[:, 1], 0.7)))),
+            Constraint(2, float(np.float32(np.quantile(sample[:, 2], 0.2))), math.inf)]
+    for k in (1, 100, 2000):
+        q = Query(w=w, constraints=cons, k=k)
+        r = eng.search(q, precision="fp32")
+        check_fp32_exact(lib_h, dec_h, q, r, f"linear k={k}")
