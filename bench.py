@@ -86,6 +86,120 @@ def cpu_baseline(lib_h, dec_h, q, target_s=15.0):
                       f"({tot} compounds) of the same library and query, {dt:.1f} s"}
 
 
+def serve_bench(eng, lib_h, n_queries, qps, prec="bf16", chunk_compounds=1 << 20, seed=4):
+    """Continuous-batching server on a seeded Poisson stream of queries over
+    reaction subsets of the library (sizes log-uniform in [1e5, 1e7] compounds),
+    against one-query-at-a-time FP32 searches on the same arrivals."""
+    import torch
+    import paper_2510_24380_amd as apex
+    import workloads.gen as gen
+    H = np.array(json.load(open(os.path.join(GOLDEN, "c1_heads_sample.json")))["heads"])
+    counts = lib_h.reaction_counts()
+    stream = gen.serving_stream(seed, n_queries, qps, counts, 1e5, 1e7, lambda h, qq: np.quantile(H[:, h], qq))
+    sizes = [sum(counts[r] for r in q.reactions) for _, q in stream]
+
+    def pct(v, p):
+        return float(np.percentile(np.array(v), p)) if v else 0.0
+
+    # 1. served, Poisson arrivals
+    srv = apex.Server(eng, pool_bytes=4 << 30, max_active=16, chunk_compounds=chunk_compounds)
+    t0 = time.perf_counter()
+    tickets = []
+    for t, q in stream:
+        dt = t0 + t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(q, precision=prec))
+    served = [srv.poll(tk, timeout_ms=600000) for tk in tickets]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    # 2. served, all submitted at once (capacity)
+    srv = apex.Server(eng, pool_bytes=4 << 30, max_active=16, chunk_compounds=chunk_compounds)
+    t1 = time.perf_counter()
+    tk2 = [srv.submit(q, precision=prec) for _, q in stream]
+    for tk in tk2:
+        srv.poll(tk, timeout_ms=600000)
+    cap_s = time.perf_counter() - t1
+    srv.close()
+    # 3. sequential FP32 on the same arrivals
+    lat, seq = [], []
+    t2 = time.perf_counter()
+    busy = 0.0
+    for t, q in stream:
+        dt = t2 + t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        a = time.perf_counter()
+        seq.append(eng.search(q, precision="fp32"))
+        busy += time.perf_counter() - a
+        lat.append((time.perf_counter() - t2 - t) * 1e3)
+    recalls = [len(set(a.ids.tolist()) & set(b.ids.tolist())) / max(1, len(b.ids)) for a, b in zip(served, seq)]
+    return {
+        "queries": n_queries, "qps": qps, "precision": prec, "chunk_compounds": chunk_compounds,
+        "library_sizes": [min(sizes), float(np.median(sizes)), max(sizes)],
+        "served": {"p50_latency_ms": st["p50_latency_ms"], "p99_latency_ms": st["p99_latency_ms"],
+                   "max_latency_ms": st["max_latency_ms"], "wall_s": wall,
+                   "device_compounds_per_s": st["compounds_per_s"],
+                   "saturated_query_compounds_per_s": sum(sizes) / cap_s},
+        "sequential_fp32": {"p50_latency_ms": pct(lat, 50), "p99_latency_ms": pct(lat, 99),
+                            "max_latency_ms": max(lat), "query_compounds_per_s": sum(sizes) / busy},
+        "recall_vs_sequential_fp32": {"mean": float(np.mean(recalls)), "min": float(np.min(recalls))},
+    }
+
+
+def main_c3(args):
+    """The streamed 2.9e10-compound library: one step is one search over all of it."""
+    import torch
+    import paper_2510_24380_amd as apex
+    import workloads.gen as gen
+    from workloads.gen import Constraint, Query
+    t0 = time.perf_counter()
+    lib_h, dec_h = gen.config_c3()
+    spec = json.load(open(os.path.join(GOLDEN, "c3_query.json")))["query"]
+    cons = [Constraint(c["head"], -math.inf if c["lo"] is None else c["lo"],
+                       math.inf if c["hi"] is None else c["hi"]) for c in spec["constraints"]]
+    q = Query(w=np.array(spec["w"], np.float32), constraints=cons, k=spec["k"])
+    tables = torch.from_numpy(lib_h.tables).cuda()
+    del lib_h.tables
+    lib = apex.Library(lib_h.n_slots, lib_h.slot_sizes, tables)
+    dec = apex.Decoder(dec_h.dims, "silu", [torch.from_numpy(w).cuda() for w in dec_h.W],
+                       [torch.from_numpy(b).cuda() for b in dec_h.b])
+    eng = apex.Engine(lib, dec, precisions=("fp32", args.precision))
+    setup_s = time.perf_counter() - t0
+    n = lib.num_compounds
+    flops_c = algorithmic_flops_per_compound(dec_h.dims)
+    for _ in range(args.warmup):
+        eng.search(q, precision=args.precision)
+    eng.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        r = eng.search(q, precision=args.precision)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / args.steps
+    ms, launches, comps = eng.profile(False)
+    achieved = flops_c * comps / (ms * 1e-3) if ms > 0 else 0.0
+    out = {
+        "metric": METRIC, "value": n / dt, "unit": "compounds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic (seeded N(0,1) synthon embeddings, Xavier-uniform decoder)",
+        "config": {"workload": "2.9e10-compound synthetic CSL streamed (2000 reactions, lognormal slot sizes median "
+                               "800 up to 10000), d=256, decoder 256->512->512 (SiLU)->15, objective = weighted sum "
+                               "of 3 heads, 6 one-sided bounds, k=10000, 4k pool rescored in FP32",
+                   "n_compounds": n, "k": q.k, "precision": args.precision},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision], "traffic": None,
+                     "kernel": "apex::k_enum (fused)", "avg_launch_ms": ms / max(launches, 1),
+                     "launches_per_step": launches / args.steps, "flops_per_compound": flops_c},
+        "results": {"n_found": len(r.ids), "candidates": r.n_candidates, "reruns": r.n_reruns,
+                    "best_ids": [int(x) for x in r.ids[:5]]},
+        "setup_s": setup_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +208,12 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--quick", action="store_true", help="headline precision only (profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3"],
+                    help="c1: 1.04e7-compound library (default); c3: 2.9e10-compound streamed library")
+    ap.add_argument("--serve-queries", type=int, default=80, help="serving stream length (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--serve-qps", type=float, default=100.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the search runs on a single MI355X; see DESIGN.md for how it shards",
@@ -107,6 +227,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "c3":
+        return main_c3(args)
     lib_h, dec_h = gen.config_c1()
     q = load_query()
     tables = torch.from_numpy(lib_h.tables).to(dev)
@@ -154,6 +276,11 @@ def main():
         err = np.abs(eng.heads(s_ids, prec).astype(np.float64) - s_h64)
         return {"max": [float(x) for x in err.max(0)], "mean": [float(x) for x in err.mean(0)]}
 
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
     head = run(args.precision, args.steps, args.warmup)
     roof = kernel_roofline(args.precision)
     others = {}
@@ -189,6 +316,9 @@ def main():
     }
     if "fp32" in others and args.precision != "fp32":
         out["speedup_vs_fp32"] = head["compounds_per_s"] / others["fp32"]["compounds_per_s"]
+    if args.serve_queries and not args.quick:
+        out["serving"] = serve_bench(eng, lib_h, args.serve_queries, args.serve_qps)
+        out["p99_latency_ms"] = out["serving"]["served"]["p99_latency_ms"]
     if not args.no_cpu_baseline and not args.quick:
         out["cpu_baseline"] = cpu_baseline(lib_h, dec_h, q)
     print(json.dumps(out), flush=True)

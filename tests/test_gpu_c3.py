@@ -1,0 +1,72 @@
+"""The streamed 2.9e10-compound library (2000 reactions, 5.3M synthon rows,
+5.4 GB of tables): exact FP32 parity with the FP64 oracle on a reaction subset
+of about 1e7 compounds (ids beyond 2^32), and a full-library BF16 search whose
+returned compounds are recomputed one by one in FP64."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads.gen as g
+from workloads.gen import Constraint, Query
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_query(subset):
+    spec = json.load(open(os.path.join(GOLDEN, "c3_query.json")))["query"]
+    cons = [Constraint(c["head"], -math.inf if c["lo"] is None else c["lo"],
+                       math.inf if c["hi"] is None else c["hi"]) for c in spec["constraints"]]
+    return Query(w=np.array(spec["w"], np.float32), constraints=cons, k=spec["k"],
+                 reactions=spec["subset"] if subset else None)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import paper_2510_24380_amd as apex
+    print("building the 2.9e10-compound library", flush=True)
+    lib_h, dec_h = g.config_c3()
+    tables = torch.from_numpy(lib_h.tables).cuda()
+    lib = apex.Library(lib_h.n_slots, lib_h.slot_sizes, tables)
+    dec = apex.Decoder(dec_h.dims, "silu", [torch.from_numpy(w).cuda() for w in dec_h.W],
+                       [torch.from_numpy(b).cuda() for b in dec_h.b])
+    eng = apex.Engine(lib, dec, precisions=("fp32", "bf16"))
+    print("engine ready", flush=True)
+    return lib_h, dec_h, lib, eng
+
+
+def test_c3_subset_fp32_exact(c3):
+    lib_h, dec_h, lib, eng = c3
+    gold = json.load(open(os.path.join(GOLDEN, "c3_oracle_subset.json")))
+    q = load_query(subset=True)
+    r = eng.search(q, precision="fp32")
+    k = min(q.k, gold["n_feasible"])
+    print(f"subset of {gold['subset_compounds']} compounds: gap_k={gold['gap_k']:.3e} "
+          f"slack={gold['min_slack_selected']:.3e} near={gold['min_violation_near']:.3e}", flush=True)
+    assert r.ids.min() > 2 ** 32 or r.ids.max() > 2 ** 32
+    assert set(r.ids.tolist()) == set(gold["ids"][:k])
+    o64 = dict(zip(gold["ids"], gold["objective"]))
+    ref = np.array([o64[i] for i in r.ids.tolist()])
+    assert np.all(np.abs(r.objective - ref) <= 1e-5 * np.maximum(np.abs(ref), 1.0))
+
+
+def test_c3_full_bf16_pointwise(c3):
+    lib_h, dec_h, lib, eng = c3
+    q = load_query(subset=False)
+    r = eng.search(q, precision="bf16")
+    print(f"full library: {len(r.ids)} results, scored {r.n_scored}, candidates {r.n_candidates}, "
+          f"reruns {r.n_reruns}", flush=True)
+    assert len(r.ids) == q.k and r.n_scored >= lib_h.n_compounds
+    pick = np.linspace(0, len(r.ids) - 1, 256).astype(np.int64)
+    h64 = oracle.heads(lib_h, dec_h, r.ids[pick])
+    o64 = h64 @ q.w.astype(np.float64)
+    assert np.all(np.abs(r.objective[pick] - o64) <= 1e-5 * np.maximum(np.abs(o64), 1.0))
+    for c in q.constraints:
+        assert np.all((h64[:, c.head] >= c.lo - 1e-5) & (h64[:, c.head] <= c.hi + 1e-5))
+    keys = list(zip((-r.objective).tolist(), r.ids.tolist()))
+    assert keys == sorted(keys)

@@ -414,3 +414,53 @@ def sample_ids(seed: int, name: str, n_total: int, n: int) -> np.ndarray:
     """n compound ids drawn uniformly (with replacement) from [0, n_total)."""
     x = stream_u64(seed, name, n)
     return (x % np.uint64(n_total)).astype(np.uint64)
+
+
+def serving_stream(seed: int, n: int, qps: float, reaction_counts: Sequence[int], size_lo: float, size_hi: float,
+                   head_quantile, n_heads: int = 15, ks=(100, 1000, 10000)):
+    """A seeded stream of queries for the serving loop.
+
+    Arrivals are a Poisson process (exponential gaps, rate qps). Each query has
+    objective weights N(0, 1) over the heads, 2-6 one-sided bounds on distinct
+    heads at quantiles drawn from [0.6, 0.9] (values from `head_quantile(head, q)`,
+    which the caller supplies), k drawn from `ks`, and a library that is a subset
+    of reactions whose compound count is drawn log-uniformly in [size_lo, size_hi]
+    (reactions added in a seeded random order until the target is reached).
+    Returns a list of (arrival_s, Query)."""
+    u = uniform_f64(seed, "serve_u", 16 * n).reshape(n, 16)
+    z = normal_f64(seed, "serve_w", n * n_heads).reshape(n, n_heads)
+    gaps = -_log(1.0 - uniform_f64(seed, "serve_gap", n)) / qps
+    t = np.cumsum(gaps)
+    T = len(reaction_counts)
+    out = []
+    for i in range(n):
+        order = np.argsort(uniform_f64(seed + 1000003 * (i + 1), "serve_perm", T), kind="stable")
+        target = math.exp(math.log(size_lo) + (math.log(size_hi) - math.log(size_lo)) * float(u[i, 0]))
+        subset, tot = [], 0
+        for r in order:
+            subset.append(int(r))
+            tot += int(reaction_counts[int(r)])
+            if tot >= target:
+                break
+        n_thr = 2 + int(u[i, 1] * 5)
+        heads = np.argsort(uniform_f64(seed + 7919 * (i + 1), "serve_heads", n_heads), kind="stable")[:n_thr]
+        cons = []
+        for j, h in enumerate(heads):
+            q = 0.6 + 0.3 * float(u[i, 2 + j])
+            if u[i, 8 + j] < 0.5:
+                cons.append(Constraint(int(h), -math.inf, float(np.float32(head_quantile(int(h), q)))))
+            else:
+                cons.append(Constraint(int(h), float(np.float32(head_quantile(int(h), 1.0 - q))), math.inf))
+        k = int(ks[min(len(ks) - 1, int(u[i, 14] * len(ks)))])
+        out.append((float(t[i]), Query(w=z[i].astype(np.float32), constraints=cons, k=k,
+                                       reactions=sorted(subset))))
+    return out
+
+
+def config_c3(seed: int = 2):
+    """The large streamed case: the C3 shape (about 2.9e10 compounds, 5.3M rows),
+    d = 256, decoder 256 -> 512 -> 512 (SiLU) -> 15. The tables take 5.4 GB."""
+    n_slots, sizes = config_c3_shape(seed)
+    lib = make_library(seed, n_slots, sizes, 256)
+    dec = make_decoder(seed, [256, 512, 512, 15], ACT_SILU)
+    return lib, dec
