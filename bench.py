@@ -216,7 +216,8 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=100.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the search runs on a single MI355X; see DESIGN.md for how it shards",
+        print("bench.py measures one GPU: the search runs on a single MI355X (a multi-GPU run would split "
+              "the reaction list into contiguous compound ranges, one per GPU, and merge the per-GPU top-k)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -16,7 +16,7 @@
 // compounds (one a, 16 consecutive b). Its layer-1 activations stay in registers
 // in the MFMA B-operand layout for the whole GEMM; the GEMM weights stream
 // through LDS in chunks of 16 output neurons, double-buffered and shared by the
-// eight waves; the final layer accumulates chunk by chunk.
+// waves of the workgroup; the final layer accumulates chunk by chunk.
 //
 // MFMA 16x16 layouts used (D = A * B with A 16 x K, B K x 16, lane l, g = l / 16):
 //   A: row l % 16, elements k = g * E .. g * E + E - 1 of the step
@@ -175,6 +175,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
   constexpr int ROW = H1 + kRowPad;
   constexpr int CHUNK = 16 * H1 * M::EB;  // bytes of one 16-neuron GEMM weight chunk
   constexpr int NPRE = (CHUNK / 16 + T - 1) / T;
+  constexpr bool FULL = (CHUNK / 16) % T == 0;  // every thread moves NPRE x 16 bytes
   constexpr int ROWS_BYTES = GATHER ? 0 : (TA + TB) * ROW * 4;
   constexpr int REGION = ROWS_BYTES > (NL == 2 ? 2 * CHUNK : 0) ? ROWS_BYTES : (NL == 2 ? 2 * CHUNK : 0);
   static_assert(NS * E == KG, "layout");
@@ -223,8 +224,16 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
     for (int i = tid; i < wo_bytes / 16; i += T) dst[i] = src[i];
     if (NL == 2)
       for (int i = tid; i < (int)H2; i += T) sB2[i] = A.pd.b2[i];
+    // gather mode stages no rows, so no later barrier precedes the first read
+    __syncthreads();
   }
   const uint4* w2g = reinterpret_cast<const uint4*>(A.pd.w2);
+  // the prefetched chunk is one SSA vector, so that it stays in registers
+  typedef uint32_t PreV __attribute__((ext_vector_type(4 * NPRE)));
+  auto pre_put = [](PreV& p, int q, uint4 w) {
+    p[4 * q] = w.x; p[4 * q + 1] = w.y; p[4 * q + 2] = w.z; p[4 * q + 3] = w.w;
+  };
+  auto pre_get = [](const PreV& p, int q) { return make_uint4(p[4 * q], p[4 * q + 1], p[4 * q + 2], p[4 * q + 3]); };
 
   uint32_t si = 0;
   SelDev S{};
@@ -238,13 +247,13 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
   }
 
   for (; v < vend; v += (GATHER ? vend : 1)) {
-    uint4 pre[NPRE];
+    PreV pre;
     // first GEMM weight chunk: loads issued now, stored after the activation phase
     if (NL == 2) {
 #pragma unroll
       for (int q = 0; q < NPRE; ++q) {
         const int i = tid + q * T;
-        if (i < CHUNK / 16) pre[q] = w2g[i];
+        if (FULL || i < CHUNK / 16) pre_put(pre, q, w2g[i]);
       }
     }
     // ---------------- locate the tile and stage its rows ----------------
@@ -287,16 +296,19 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
     }
 
     // ---------------- layer-1 activations into registers ----------------
+    // Row pointers first; then k-step outermost, rows innermost, so that a
+    // B-row value shared by the R rows of a wave is consumed right after its load.
     Frag X[R][NS];
+    const float* pa[R];
+    const float* pa1[R];
+    const float* pb[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float* pa;
-      const float* pa1 = nullptr;
-      const float* pb;
+      pa1[r] = nullptr;
       if (!GATHER) {
         const int aL = wave * R + r;
-        pa = sA + aL * ROW + g * KG;
-        pb = sB + j * ROW + g * KG;
+        pa[r] = sA + aL * ROW + g * KG;
+        pb[r] = sB + j * ROW + g * KG;
       } else {
         uint64_t item = v + (uint64_t)(wave * R + r) * 16 + j;
         item = item < A.n_ids ? item : (uint64_t)A.n_ids - 1;
@@ -310,43 +322,52 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
         const uint32_t b = (uint32_t)(loc % rr.nB);
         if (rr.three) {
           const uint32_t i0 = a / rr.n1, i1 = a - i0 * rr.n1;
-          pa = A.P + (uint64_t)(rr.row0 + i0) * H1 + g * KG;
-          pa1 = A.P + (uint64_t)(rr.row1 + i1) * H1 + g * KG;
+          pa[r] = A.P + (uint64_t)(rr.row0 + i0) * H1 + g * KG;
+          pa1[r] = A.P + (uint64_t)(rr.row1 + i1) * H1 + g * KG;
         } else {
-          pa = A.P + (uint64_t)(rr.row0 + a) * H1 + g * KG;
+          pa[r] = A.P + (uint64_t)(rr.row0 + a) * H1 + g * KG;
         }
-        pb = A.P + (uint64_t)(rr.rowB + b) * H1 + g * KG;
+        pb[r] = A.P + (uint64_t)(rr.rowB + b) * H1 + g * KG;
       }
-      if constexpr (E == 1) {
-        // fp32: one activation per step, four steps per 16-byte read
+    }
+    if constexpr (E == 1) {
+      // fp32: one activation per step, four steps per 16-byte read
 #pragma unroll
-        for (int s4 = 0; s4 < NS / 4; ++s4) {
-          float4 xa = *reinterpret_cast<const float4*>(pa + 4 * s4);
-          if (GATHER && pa1) {
-            const float4 xq = *reinterpret_cast<const float4*>(pa1 + 4 * s4);
+      for (int s4 = 0; s4 < NS / 4; ++s4) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float4 xa = *reinterpret_cast<const float4*>(pa[r] + 4 * s4);
+          if (GATHER && pa1[r]) {
+            const float4 xq = *reinterpret_cast<const float4*>(pa1[r] + 4 * s4);
             xa = make_float4(xa.x + xq.x, xa.y + xq.y, xa.z + xq.z, xa.w + xq.w);
           }
-          const float4 xb = *reinterpret_cast<const float4*>(pb + 4 * s4);
+          const float4 xb = *reinterpret_cast<const float4*>(pb[r] + 4 * s4);
           X[r][4 * s4 + 0] = act_pre<ACT>(xa.x + xb.x);
           X[r][4 * s4 + 1] = act_pre<ACT>(xa.y + xb.y);
           X[r][4 * s4 + 2] = act_pre<ACT>(xa.z + xb.z);
           X[r][4 * s4 + 3] = act_pre<ACT>(xa.w + xb.w);
+          asm volatile("" : "+v"(X[r][4 * s4 + 0]), "+v"(X[r][4 * s4 + 1]), "+v"(X[r][4 * s4 + 2]),
+                       "+v"(X[r][4 * s4 + 3])::"memory");
         }
-      } else {
+      }
+    } else {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
+      for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
           Frag f;
 #pragma unroll
           for (int e4 = 0; e4 < E / 4; ++e4) {
-            float4 xa = *reinterpret_cast<const float4*>(pa + s * E + 4 * e4);
-            if (GATHER && pa1) {
-              const float4 xq = *reinterpret_cast<const float4*>(pa1 + s * E + 4 * e4);
+            float4 xa = *reinterpret_cast<const float4*>(pa[r] + s * E + 4 * e4);
+            if (GATHER && pa1[r]) {
+              const float4 xq = *reinterpret_cast<const float4*>(pa1[r] + s * E + 4 * e4);
               xa = make_float4(xa.x + xq.x, xa.y + xq.y, xa.z + xq.z, xa.w + xq.w);
             }
-            const float4 xb = *reinterpret_cast<const float4*>(pb + s * E + 4 * e4);
+            const float4 xb = *reinterpret_cast<const float4*>(pb[r] + s * E + 4 * e4);
             Pack<PREC>::put4(f, e4, act_pre<ACT>(xa.x + xb.x), act_pre<ACT>(xa.y + xb.y),
                              act_pre<ACT>(xa.z + xb.z), act_pre<ACT>(xa.w + xb.w), XS);
           }
+          asm volatile("" : "+v"(f)::"memory");
           X[r][s] = f;
         }
       }
@@ -381,7 +402,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
 #pragma unroll
         for (int q = 0; q < NPRE; ++q) {
           const int i = tid + q * T;
-          if (i < CHUNK / 16) dst[i] = pre[q];
+          if (FULL || i < CHUNK / 16) dst[i] = pre_get(pre, q);
         }
       }
       __syncthreads();
@@ -391,12 +412,14 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
       // of the final layer) from `prev`; the two are independent, so the
       // activation's VALU work overlaps the MFMAs.
       uint32_t tprev[R][2];  // even chunk of a pair, packed bf16 (bf16/fp8 final layer)
-      auto gemm = [&](int c, f32x4 (&acc)[R]) {
-        if (c + 1 < NC) {
+      // pf: chunk c + 1 exists; a literal at every call, so the pipelined loop
+      // body below has no branches and the scheduler can interleave its parts.
+      auto gemm = [&](int c, f32x4 (&acc)[R], bool pf) {
+        if (pf) {
 #pragma unroll
           for (int q = 0; q < NPRE; ++q) {
             const int i = tid + q * T;
-            if (i < CHUNK / 16) pre[q] = w2g[(size_t)(c + 1) * (CHUNK / 16) + i];
+            if (FULL || i < CHUNK / 16) pre_put(pre, q, w2g[(size_t)(c + 1) * (CHUNK / 16) + i]);
           }
         }
         const f32x4 binit = *reinterpret_cast<const f32x4*>(sB2 + c * 16 + g * 4);
@@ -449,30 +472,30 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_enum(EnumArgs A) {
           }
         }
       };
-      auto publish = [&](int c) {  // prefetched chunk c + 1 -> its LDS buffer
-        if (c + 1 < NC) {
+      auto publish = [&](int c, bool pf) {  // prefetched chunk c + 1 -> its LDS buffer
+        if (pf) {
           uint4* dst = reinterpret_cast<uint4*>(sW + ((c + 1) & 1) * CHUNK);
 #pragma unroll
           for (int q = 0; q < NPRE; ++q) {
             const int i = tid + q * T;
-            if (i < CHUNK / 16) dst[i] = pre[q];
+            if (FULL || i < CHUNK / 16) dst[i] = pre_get(pre, q);
           }
         }
         __syncthreads();
       };
       f32x4 accA[R], accB[R];
-      gemm(0, accA);
-      publish(0);
+      gemm(0, accA, true);  // NC >= 2
+      publish(0, true);
       int c = 1;
-      for (; c + 1 < NC; c += 2) {
-        gemm(c, accB);
+      for (; c + 1 < NC; c += 2) {  // chunks c + 1 and c + 2 <= NC - 1 exist
+        gemm(c, accB, true);
         finish(c - 1, accA, false);
-        publish(c);
-        gemm(c + 1, accA);
+        publish(c, true);
+        gemm(c + 1, accA, true);
         finish(c, accB, true);
-        publish(c + 1);
+        publish(c + 1, true);
       }
-      gemm(c, accB);  // c == NC - 1 (NC is even)
+      gemm(c, accB, false);  // c == NC - 1 (NC is even)
       finish(c - 1, accA, false);
       finish(c, accB, true);
       __syncthreads();  // the region is restaged by the next tile
