@@ -27,6 +27,38 @@ sys.path.insert(0, ROOT)
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}  # dense MFMA, MI355X
 METRIC = "compounds/s scored+top-k, BF16/FP8 vs FP32 @ recall@k>=0.99; p99 query latency"
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_2510_24380_amd/csrc/enum_kernel.h", "paper_2510_24380_amd/csrc/apex_internal.h",
+                  "paper_2510_24380_amd/csrc/enum_{prec}.hip"]
+
+
+def kernel_sources_sha256(prec):
+    """Hash of the sources that define the fused kernel of one precision."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, rel.format(prec=prec)), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec, workload="c1"):
+    """HBM bytes per launch of the fused kernel from the committed hardware-counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
+    None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(PROFILES, f"k_enum_{prec}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip("` ")] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256(prec):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_flops_per_compound(dims):
@@ -264,7 +296,8 @@ def main():
         flops_launch = flops_c * comps / max(launches, 1)
         achieved = flops_launch / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
         return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[prec], "traffic": None, "kernel": "apex::k_enum (fused)",
+                "frac": achieved / PEAK[prec], "traffic": measured_traffic(prec), "traffic_unit": "bytes/launch",
+                "kernel": "apex::k_enum (fused)",
                 "avg_launch_ms": avg_ms, "launches_per_step": launches / steps,
                 "compounds_per_launch": comps / max(launches, 1), "flops_per_compound": flops_c}
 

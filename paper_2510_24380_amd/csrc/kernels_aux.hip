@@ -218,14 +218,19 @@ __device__ inline float objective16(const float* w, const float* h) {
 }
 
 // Scores listed compounds for each query (objective, bounds, the query's reaction
-// subset, threshold) and appends the passing ones to its candidate buffer with
-// one atomic per wave.
-__global__ void k_score(const float* __restrict__ heads, const uint64_t* __restrict__ ids, uint32_t n,
-                        const QueryDev* __restrict__ qs, uint32_t nq, const ReactDev* __restrict__ react,
-                        uint32_t n_react) {
+// subset, threshold) and appends the passing ones to its candidate buffer. The
+// appends of a workgroup take one atomic on the query's counter (a wave prefix
+// in LDS), so a sample in which most compounds pass does not serialise on it.
+constexpr int kScoreThreads = 1024;
+__global__ __launch_bounds__(kScoreThreads) void k_score(const float* __restrict__ heads,
+                                                        const uint64_t* __restrict__ ids, uint32_t n,
+                                                        const QueryDev* __restrict__ qs, uint32_t nq,
+                                                        const ReactDev* __restrict__ react, uint32_t n_react) {
+  __shared__ uint32_t wave_count[kScoreThreads / 64];
+  __shared__ uint32_t block_base;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t q = blockIdx.y;
-  if (q >= nq) return;
+  if (q >= nq) return;  // uniform per workgroup
   const QueryDev* Q = qs + q;
   if (!Q->active) return;
   bool pass = false;
@@ -237,8 +242,15 @@ __global__ void k_score(const float* __restrict__ heads, const uint64_t* __restr
   }
   if (i < n && id != ~0ull) {
     float h[kHeadsPad];
+    const float4* h4 = reinterpret_cast<const float4*>(heads + (uint64_t)i * kHeadsPad);
 #pragma unroll
-    for (int k = 0; k < kHeadsPad; ++k) h[k] = heads[(uint64_t)i * kHeadsPad + k];
+    for (int k4 = 0; k4 < kHeadsPad / 4; ++k4) {
+      const float4 v = h4[k4];
+      h[4 * k4] = v.x;
+      h[4 * k4 + 1] = v.y;
+      h[4 * k4 + 2] = v.z;
+      h[4 * k4 + 3] = v.w;
+    }
     o = objective16(Q->w, h);
     bool ok = o == o;
 #pragma unroll
@@ -247,19 +259,55 @@ __global__ void k_score(const float* __restrict__ heads, const uint64_t* __restr
     pass = ok && key_passes(o, id, Q->st->tau_o, Q->st->tau_id);
   }
   const uint64_t m = __ballot(pass);
-  if (m) {
-    const uint32_t lane = threadIdx.x & 63;
-    uint32_t base = 0;
-    const uint32_t first = (uint32_t)__ffsll((long long)m) - 1;
-    if (lane == first) base = atomicAdd(&Q->st->count, (uint32_t)__popcll(m));
-    base = __shfl(base, (int)first);
-    if (pass) {
-      const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-      const uint32_t idx = base + (uint32_t)__popcll(m & below);
-      if (idx < Q->cap) {
-        Q->cand_o[idx] = o;
-        Q->cand_id[idx] = id;
-      }
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) wave_count[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kScoreThreads / 64; ++w) tot += wave_count[w];
+    block_base = tot ? atomicAdd(&Q->st->count, tot) : 0u;
+  }
+  __syncthreads();
+  if (pass) {
+    uint32_t base = block_base;
+    for (uint32_t w = 0; w < wave; ++w) base += wave_count[w];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t idx = base + (uint32_t)__popcll(m & below);
+    if (idx < Q->cap) {
+      Q->cand_o[idx] = o;
+      Q->cand_id[idx] = id;
+    }
+  }
+}
+
+// Heads of the final answer of a low-precision search: every answer id is one of
+// the rescored pool's ids, whose FP32 heads were already computed; each thread
+// finds its id in LDS tiles of the pool and copies that row.
+constexpr int kLookupThreads = 256;
+__global__ __launch_bounds__(kLookupThreads) void k_pool_lookup(const uint64_t* __restrict__ pool_id,
+                                                               const float* __restrict__ pool_heads,
+                                                               uint32_t n_pool, const uint64_t* __restrict__ want,
+                                                               uint32_t n_want, float* __restrict__ out) {
+  __shared__ uint64_t tile[kLookupThreads];
+  const uint32_t i = blockIdx.x * kLookupThreads + threadIdx.x;
+  const uint64_t id = i < n_want ? want[i] : ~0ull;
+  uint32_t found = UINT32_MAX;
+  for (uint32_t base = 0; base < n_pool; base += kLookupThreads) {
+    const uint32_t j = base + threadIdx.x;
+    tile[threadIdx.x] = j < n_pool ? pool_id[j] : ~0ull;
+    __syncthreads();
+    const uint32_t lim = n_pool - base < (uint32_t)kLookupThreads ? n_pool - base : (uint32_t)kLookupThreads;
+    for (uint32_t t = 0; t < lim; ++t)
+      if (tile[t] == id) found = base + t;
+    __syncthreads();
+  }
+  if (i < n_want) {
+    float4* dst = reinterpret_cast<float4*>(out + (uint64_t)i * kHeadsPad);
+    if (found != UINT32_MAX) {
+      const float4* src = reinterpret_cast<const float4*>(pool_heads + (uint64_t)found * kHeadsPad);
+      for (int k4 = 0; k4 < kHeadsPad / 4; ++k4) dst[k4] = src[k4];
+    } else {
+      for (int k4 = 0; k4 < kHeadsPad / 4; ++k4) dst[k4] = make_float4(NAN, NAN, NAN, NAN);
     }
   }
 }
@@ -279,7 +327,29 @@ __device__ inline float unord_f32(uint32_t k) {
   return __uint_as_float(u);
 }
 
-__global__ __launch_bounds__(1024) void k_select(const QueryDev* __restrict__ qs, uint32_t chunk_id, int force) {
+// Adds one to hist[digit] for every active lane. Lanes of a wave that share a
+// digit add together (candidate keys are nearly sorted by magnitude, so most of
+// a wave falls into one or two bins and plain LDS atomics would serialise);
+// the few lanes left after four rounds add individually. Every lane of the
+// wave must call it.
+__device__ inline void hist_add(uint32_t* hist, uint32_t digit, bool active) {
+  const uint32_t lane = threadIdx.x & 63;
+  bool pending = active;
+  for (int it = 0; it < 4; ++it) {
+    const uint64_t todo = __ballot(pending);
+    if (!todo) return;
+    const int leader = __ffsll((long long)todo) - 1;
+    const uint32_t d = (uint32_t)__shfl((int)digit, leader);
+    const bool mine = pending && digit == d;
+    const uint64_t same = __ballot(mine);
+    if ((int)lane == leader) atomicAdd(&hist[d], (uint32_t)__popcll(same));
+    pending = pending && !mine;
+  }
+  if (pending) atomicAdd(&hist[digit], 1u);
+}
+
+__global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __restrict__ qs, uint32_t chunk_id,
+                                                          int force) {
   const QueryDev Q = qs[blockIdx.x];
   if (!Q.active) return;
   QState* st = Q.st;
@@ -300,14 +370,16 @@ __global__ __launch_bounds__(1024) void k_select(const QueryDev* __restrict__ qs
     }
     return;
   }
+  // every loop below runs the same number of iterations in all lanes (ballots)
+  const uint32_t n_pad = (n + kSelectThreads - 1) / kSelectThreads * kSelectThreads;
   // ---- K-th largest order key of the objective ----
   uint32_t prefix = 0, pmask = 0, need = K;
   for (int shift = 24; shift >= 0; shift -= 8) {
-    for (uint32_t b = tid; b < 256; b += blockDim.x) hist[b] = 0;
+    for (uint32_t b = tid; b < 256; b += kSelectThreads) hist[b] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += blockDim.x) {
-      const uint32_t kf = ord_f32(Q.cand_o[i]);
-      if ((kf & pmask) == prefix) atomicAdd(&hist[(kf >> shift) & 255u], 1u);
+    for (uint32_t i = tid; i < n_pad; i += kSelectThreads) {
+      const uint32_t kf = i < n ? ord_f32(Q.cand_o[i]) : 0u;
+      hist_add(hist, (kf >> shift) & 255u, i < n && (kf & pmask) == prefix);
     }
     __syncthreads();
     if (tid == 0) {
@@ -335,12 +407,12 @@ __global__ __launch_bounds__(1024) void k_select(const QueryDev* __restrict__ qs
     uint64_t ip = 0, im = 0;
     uint32_t want = need;
     for (int shift = 56; shift >= 0; shift -= 8) {
-      for (uint32_t b = tid; b < 256; b += blockDim.x) hist[b] = 0;
+      for (uint32_t b = tid; b < 256; b += kSelectThreads) hist[b] = 0;
       __syncthreads();
-      for (uint32_t i = tid; i < n; i += blockDim.x) {
-        if (ord_f32(Q.cand_o[i]) != T) continue;
-        const uint64_t id = Q.cand_id[i];
-        if ((id & im) == ip) atomicAdd(&hist[(id >> shift) & 255u], 1u);
+      for (uint32_t i = tid; i < n_pad; i += kSelectThreads) {
+        const bool tie = i < n && ord_f32(Q.cand_o[i]) == T;
+        const uint64_t id = tie ? Q.cand_id[i] : 0ull;
+        hist_add(hist, (uint32_t)(id >> shift) & 255u, tie && (id & im) == ip);
       }
       __syncthreads();
       if (tid == 0) {
@@ -373,15 +445,27 @@ __global__ __launch_bounds__(1024) void k_select(const QueryDev* __restrict__ qs
     }
     return;
   }
-  // ---- compaction to exactly K entries ----
+  // ---- compaction to exactly K entries (one LDS atomic per wave) ----
   if (tid == 0) s_pos = 0;
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += blockDim.x) {
-    const float o = Q.cand_o[i];
-    const uint32_t kf = ord_f32(o);
-    const uint64_t id = Q.cand_id[i];
-    if (kf > T || (kf == T && id <= I)) {
-      const uint32_t p = atomicAdd(&s_pos, 1u);
+  const uint32_t lane = tid & 63;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (uint32_t i = tid; i < n_pad; i += kSelectThreads) {
+    float o = 0.0f;
+    uint64_t id = 0;
+    bool keep = false;
+    if (i < n) {
+      o = Q.cand_o[i];
+      id = Q.cand_id[i];
+      const uint32_t kf = ord_f32(o);
+      keep = kf > T || (kf == T && id <= I);
+    }
+    const uint64_t m = __ballot(keep);
+    uint32_t wbase = 0;
+    if (lane == 0 && m) wbase = atomicAdd(&s_pos, (uint32_t)__popcll(m));
+    wbase = (uint32_t)__shfl((int)wbase, 0);
+    if (keep) {
+      const uint32_t p = wbase + (uint32_t)__popcll(m & below);
       if (p < K) {
         Q.tmp_o[p] = o;
         Q.tmp_id[p] = id;
@@ -389,7 +473,7 @@ __global__ __launch_bounds__(1024) void k_select(const QueryDev* __restrict__ qs
     }
   }
   __syncthreads();
-  for (uint32_t i = tid; i < K; i += blockDim.x) {
+  for (uint32_t i = tid; i < K; i += kSelectThreads) {
     Q.cand_o[i] = Q.tmp_o[i];
     Q.cand_id[i] = Q.tmp_id[i];
   }
@@ -565,7 +649,16 @@ hipError_t launch_bias(const float* b2, uint32_t h2, float c, const float* scal,
 hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,
                         const ReactDev* react, uint32_t n_react, hipStream_t s) {
   if (n == 0 || nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_score, dim3((n + 255) / 256, nq), dim3(256), 0, s, heads, ids, n, qs, nq, react, n_react);
+  hipLaunchKernelGGL(k_score, dim3((n + kScoreThreads - 1) / kScoreThreads, nq), dim3(kScoreThreads), 0, s, heads,
+                     ids, n, qs, nq, react, n_react);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, uint32_t n_pool, const uint64_t* want,
+                              uint32_t n_want, float* out, hipStream_t s) {
+  if (n_want == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool_lookup, dim3((n_want + kLookupThreads - 1) / kLookupThreads), dim3(kLookupThreads), 0, s,
+                     pool_id, pool_heads, n_pool, want, n_want, out);
   return hipGetLastError();
 }
 

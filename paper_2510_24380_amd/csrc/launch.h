@@ -25,6 +25,8 @@ hipError_t launch_bias(const float* b2, uint32_t h2, float c, const float* scal,
                        float* b2_out, float* bo_out, hipStream_t s);
 hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,
                         const ReactDev* react, uint32_t n_react, hipStream_t s);
+hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, uint32_t n_pool, const uint64_t* want,
+                              uint32_t n_want, float* out, hipStream_t s);
 hipError_t launch_select(const QueryDev* qs, uint32_t nq, uint32_t chunk_id, int force, hipStream_t s);
 hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s);
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,

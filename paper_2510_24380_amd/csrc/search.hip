@@ -327,8 +327,12 @@ apex_status finish_query(apex_engine* E, const apex_query* q, const QPlan& P, co
   res->n_candidates = st1.appended;
   if (n_found == 0) return APEX_OK;
   std::vector<float> heads;
-  apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, n_found, P.fin_heads, s);
-  if (st != APEX_OK) return st;
+  if (P.lowp) {  // the answer is part of the rescored pool
+    HIP_TRY(launch_pool_lookup(P.cand_id, P.pool_heads, n1, P.fin_id, n_found, P.fin_heads, s));
+  } else {
+    apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, n_found, P.fin_heads, s);
+    if (st != APEX_OK) return st;
+  }
   HIP_TRY(launch_decode(E->react, E->lib->T, P.fin_id, P.lowp ? P.st2 : P.st, P.k, P.fin_reaction, P.fin_synthon,
                         s));
   HIP_TRY(hipMemcpyAsync(res->ids, P.fin_id, sizeof(uint64_t) * n_found, hipMemcpyDeviceToHost, s));
