@@ -281,34 +281,31 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const float* __restrict
 }
 
 // Heads of the final answer of a low-precision search: every answer id is one of
-// the rescored pool's ids, whose FP32 heads were already computed; each thread
-// finds its id in LDS tiles of the pool and copies that row.
+// the rescored pool's ids, whose FP32 heads were already computed; the row of
+// each answer id is found in LDS tiles of the pool and copied.
 constexpr int kLookupThreads = 256;
+constexpr uint32_t kLookupTile = 2048;  // pool ids per workgroup
 __global__ __launch_bounds__(kLookupThreads) void k_pool_lookup(const uint64_t* __restrict__ pool_id,
                                                                const float* __restrict__ pool_heads,
                                                                uint32_t n_pool, const uint64_t* __restrict__ want,
                                                                uint32_t n_want, float* __restrict__ out) {
-  __shared__ uint64_t tile[kLookupThreads];
+  // grid: x over the wanted ids, y over tiles of the pool; the one workgroup
+  // whose tile holds an id writes its row
+  __shared__ uint64_t tile[kLookupTile];
+  const uint32_t base = blockIdx.y * kLookupTile;
+  const uint32_t lim = n_pool - base < kLookupTile ? n_pool - base : kLookupTile;
+  for (uint32_t t = threadIdx.x; t < kLookupTile; t += kLookupThreads) tile[t] = t < lim ? pool_id[base + t] : ~0ull;
+  __syncthreads();
   const uint32_t i = blockIdx.x * kLookupThreads + threadIdx.x;
-  const uint64_t id = i < n_want ? want[i] : ~0ull;
+  if (i >= n_want) return;
+  const uint64_t id = want[i];
   uint32_t found = UINT32_MAX;
-  for (uint32_t base = 0; base < n_pool; base += kLookupThreads) {
-    const uint32_t j = base + threadIdx.x;
-    tile[threadIdx.x] = j < n_pool ? pool_id[j] : ~0ull;
-    __syncthreads();
-    const uint32_t lim = n_pool - base < (uint32_t)kLookupThreads ? n_pool - base : (uint32_t)kLookupThreads;
-    for (uint32_t t = 0; t < lim; ++t)
-      if (tile[t] == id) found = base + t;
-    __syncthreads();
-  }
-  if (i < n_want) {
+  for (uint32_t t = 0; t < lim; ++t)
+    if (tile[t] == id) found = base + t;
+  if (found != UINT32_MAX) {
+    const float4* src = reinterpret_cast<const float4*>(pool_heads + (uint64_t)found * kHeadsPad);
     float4* dst = reinterpret_cast<float4*>(out + (uint64_t)i * kHeadsPad);
-    if (found != UINT32_MAX) {
-      const float4* src = reinterpret_cast<const float4*>(pool_heads + (uint64_t)found * kHeadsPad);
-      for (int k4 = 0; k4 < kHeadsPad / 4; ++k4) dst[k4] = src[k4];
-    } else {
-      for (int k4 = 0; k4 < kHeadsPad / 4; ++k4) dst[k4] = make_float4(NAN, NAN, NAN, NAN);
-    }
+    for (int k4 = 0; k4 < kHeadsPad / 4; ++k4) dst[k4] = src[k4];
   }
 }
 
@@ -348,6 +345,37 @@ __device__ inline void hist_add(uint32_t* hist, uint32_t digit, bool active) {
   if (pending) atomicAdd(&hist[digit], 1u);
 }
 
+// Calls f(value, index, valid) for every index in [0, n) of a candidate
+// objective array, with all lanes of the workgroup in step (f may use ballots).
+// Each thread keeps four 16-byte loads in flight, so that one workgroup moves
+// enough bytes to stay off the memory latency.
+template <class F>
+__device__ inline void scan_objectives(const float* __restrict__ o, uint32_t n, F&& f) {
+  constexpr uint32_t U = 4;
+  const uint32_t nq = n / 4;
+  const float4* o4 = reinterpret_cast<const float4*>(o);
+  for (uint32_t base = 0; base < nq; base += U * kSelectThreads) {
+    float4 v[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint32_t qi = base + u * kSelectThreads + threadIdx.x;
+      v[u] = qi < nq ? o4[qi] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint32_t qi = base + u * kSelectThreads + threadIdx.x;
+      const bool ok = qi < nq;
+      f(v[u].x, 4 * qi, ok);
+      f(v[u].y, 4 * qi + 1, ok);
+      f(v[u].z, 4 * qi + 2, ok);
+      f(v[u].w, 4 * qi + 3, ok);
+    }
+  }
+  const uint32_t i = 4 * nq + threadIdx.x;  // the last n % 4 entries
+  const bool ok = i < n;
+  f(ok ? o[i] : 0.f, i, ok);
+}
+
 __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __restrict__ qs, uint32_t chunk_id,
                                                           int force) {
   const QueryDev Q = qs[blockIdx.x];
@@ -370,17 +398,15 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
     }
     return;
   }
-  // every loop below runs the same number of iterations in all lanes (ballots)
-  const uint32_t n_pad = (n + kSelectThreads - 1) / kSelectThreads * kSelectThreads;
   // ---- K-th largest order key of the objective ----
   uint32_t prefix = 0, pmask = 0, need = K;
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (uint32_t b = tid; b < 256; b += kSelectThreads) hist[b] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < n_pad; i += kSelectThreads) {
-      const uint32_t kf = i < n ? ord_f32(Q.cand_o[i]) : 0u;
-      hist_add(hist, (kf >> shift) & 255u, i < n && (kf & pmask) == prefix);
-    }
+    scan_objectives(Q.cand_o, n, [&](float o, uint32_t, bool ok) {
+      const uint32_t kf = ord_f32(o);
+      hist_add(hist, (kf >> shift) & 255u, ok && (kf & pmask) == prefix);
+    });
     __syncthreads();
     if (tid == 0) {
       uint32_t cum = 0;
@@ -409,11 +435,11 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
     for (int shift = 56; shift >= 0; shift -= 8) {
       for (uint32_t b = tid; b < 256; b += kSelectThreads) hist[b] = 0;
       __syncthreads();
-      for (uint32_t i = tid; i < n_pad; i += kSelectThreads) {
-        const bool tie = i < n && ord_f32(Q.cand_o[i]) == T;
+      scan_objectives(Q.cand_o, n, [&](float o, uint32_t i, bool ok) {
+        const bool tie = ok && ord_f32(o) == T;
         const uint64_t id = tie ? Q.cand_id[i] : 0ull;
         hist_add(hist, (uint32_t)(id >> shift) & 255u, tie && (id & im) == ip);
-      }
+      });
       __syncthreads();
       if (tid == 0) {
         uint32_t cum = 0;
@@ -450,16 +476,11 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
   __syncthreads();
   const uint32_t lane = tid & 63;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (uint32_t i = tid; i < n_pad; i += kSelectThreads) {
-    float o = 0.0f;
-    uint64_t id = 0;
-    bool keep = false;
-    if (i < n) {
-      o = Q.cand_o[i];
-      id = Q.cand_id[i];
-      const uint32_t kf = ord_f32(o);
-      keep = kf > T || (kf == T && id <= I);
-    }
+  scan_objectives(Q.cand_o, n, [&](float o, uint32_t i, bool ok) {
+    const uint32_t kf = ord_f32(o);
+    const bool cand = ok && kf >= T;
+    const uint64_t id = cand ? Q.cand_id[i] : 0ull;
+    const bool keep = cand && (kf > T || id <= I);
     const uint64_t m = __ballot(keep);
     uint32_t wbase = 0;
     if (lane == 0 && m) wbase = atomicAdd(&s_pos, (uint32_t)__popcll(m));
@@ -471,7 +492,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
         Q.tmp_id[p] = id;
       }
     }
-  }
+  });
   __syncthreads();
   for (uint32_t i = tid; i < K; i += kSelectThreads) {
     Q.cand_o[i] = Q.tmp_o[i];
@@ -513,23 +534,42 @@ __global__ __launch_bounds__(256) void k_rank_sort(const QueryDev* __restrict__ 
                                                    uint64_t* __restrict__ out_id) {
   const QueryDev& Q = qs[q];
   const uint32_t n = min(Q.st->count, Q.K);
-  __shared__ float so[1024];
-  __shared__ uint64_t sid[1024];
+  constexpr uint32_t TILE = 1024;
+  __shared__ __attribute__((aligned(16))) float so[TILE];
+  __shared__ __attribute__((aligned(16))) uint64_t sid[TILE];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool mine = i < n;
   const float o = mine ? Q.cand_o[i] : 0.0f;
   const uint64_t id = mine ? Q.cand_id[i] : 0;
   uint32_t rank = 0;
-  for (uint32_t t0 = 0; t0 < n; t0 += 1024) {
+  for (uint32_t t0 = 0; t0 < n; t0 += TILE) {
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < 1024 && t0 + k < n; k += blockDim.x) {
-      so[k] = Q.cand_o[t0 + k];
-      sid[k] = Q.cand_id[t0 + k];
+    // entries past n are (-inf, max id): they never rank before anything
+    for (uint32_t k = threadIdx.x; k < TILE; k += blockDim.x) {
+      const bool in = t0 + k < n;
+      so[k] = in ? Q.cand_o[t0 + k] : -INFINITY;
+      sid[k] = in ? Q.cand_id[t0 + k] : ~0ull;
     }
     __syncthreads();
-    const uint32_t m = min(1024u, n - t0);
-    if (mine)
-      for (uint32_t k = 0; k < m; ++k) rank += (so[k] > o) || (so[k] == o && sid[k] < id);
+    const uint32_t m = (min(TILE, n - t0) + 15u) & ~15u;
+    if (mine) {
+      const float4* so4 = reinterpret_cast<const float4*>(so);
+      for (uint32_t k = 0; k < m; k += 16) {
+        float4 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = so4[k / 4 + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float v[4] = {a[u].x, a[u].y, a[u].z, a[u].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float x = v[e];
+            rank += x > o;
+            if (x == o) rank += sid[k + 4 * u + e] < id;
+          }
+        }
+      }
+    }
   }
   if (mine) {
     out_o[rank] = o;
@@ -657,8 +697,10 @@ hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, con
 hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, uint32_t n_pool, const uint64_t* want,
                               uint32_t n_want, float* out, hipStream_t s) {
   if (n_want == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool_lookup, dim3((n_want + kLookupThreads - 1) / kLookupThreads), dim3(kLookupThreads), 0, s,
-                     pool_id, pool_heads, n_pool, want, n_want, out);
+  if (n_pool == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pool_lookup,
+                     dim3((n_want + kLookupThreads - 1) / kLookupThreads, (n_pool + kLookupTile - 1) / kLookupTile),
+                     dim3(kLookupThreads), 0, s, pool_id, pool_heads, n_pool, want, n_want, out);
   return hipGetLastError();
 }
 
