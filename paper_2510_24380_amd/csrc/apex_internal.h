@@ -11,21 +11,20 @@ constexpr int kRowPad = 4;             // LDS row padding (floats) for staged sy
 constexpr int kHeadsPad = 16;          // heads are padded to one 16-wide MFMA tile
 constexpr uint32_t kSelectThreads = 1024;
 
-// Workgroup and tile geometry of the fused kernel per precision. Every wave
-// holds R blocks of 16 compounds; a block is one "A" row (slot 0, or slots 0 and
-// 1 of a three-slot reaction) against 16 consecutive "B" rows (the last slot).
-// A tile is TA A-rows x 16 B-rows. BF16 and FP8 use 4-wave workgroups small
-// enough in LDS for two to share a CU.
+// Workgroup and tile geometry of the fused kernels. A tile is TA "A" rows (slot
+// 0, or slots 0 and 1 of a three-slot reaction) against 16 consecutive "B" rows
+// (the last slot). FP32 (16x16 MFMA kernel): 8 waves of 16 compounds each (one
+// A-row, 16 B-rows). BF16 and FP8 (32x32 MFMA kernel): 4 waves of 32 compounds
+// each (two A-rows, 16 B-rows), small enough in LDS for two workgroups per CU.
 template <int PREC> struct TileShape;
 template <> struct TileShape<APEX_PREC_FP32> { static constexpr int W = 8, R = 1, TA = 8; };
-template <> struct TileShape<APEX_PREC_BF16> { static constexpr int W = 4, R = 2, TA = 8; };
-template <> struct TileShape<APEX_PREC_FP8> { static constexpr int W = 4, R = 3, TA = 12; };
 constexpr int kTileB = 16;
 
-inline int tile_ta(int prec) { return prec == APEX_PREC_FP32 ? 8 : (prec == APEX_PREC_BF16 ? 8 : 12); }
+inline int tile_ta(int) { return 8; }
 inline int tile_tb(int) { return kTileB; }
 inline int enum_waves(int prec) { return prec == APEX_PREC_FP32 ? 8 : 4; }
-inline int enum_rows(int prec) { return prec == APEX_PREC_FP32 ? 1 : (prec == APEX_PREC_BF16 ? 2 : 3); }
+// blocks of 16 compounds per wave
+inline int enum_rows(int prec) { return prec == APEX_PREC_FP32 ? 1 : 2; }
 
 // One reaction of the library as the kernels see it: every compound is a pair
 // (a, b) with a over the first slot(s) and b over the last slot.
@@ -51,7 +50,7 @@ struct SelDev {
 
 // Per-precision decoder state resident in the engine workspace.
 struct PrecDev {
-  const void* w2;      // GEMM2 fragments [H2/16][H1/KS][64][E] (n_layers == 3)
+  const void* w2;      // GEMM2 fragments [chunks][H1/KS][64][E] (n_layers == 3)
   const void* wo;      // final-layer fragments
   const float* b2;     // GEMM2 accumulator initial values [H2]
   const float* bo;     // final bias [16]

@@ -227,13 +227,18 @@ void engine_layout(apex_engine* E, const apex_library* L, const apex_decoder* D,
     S.on = (mask >> p) & 1u;
     if (!S.on) continue;
     const int eb = elem_bytes(p);
+    // FP32 runs the 16x16 kernel (16 padded heads), BF16/FP8 the 32x32 one (32)
+    const size_t head_rows = p == APEX_PREC_FP32 ? 16 : 32;
+    // the 32x32 kernel runs GEMM chunks in pairs: its width is padded to 64
+    // with zero neurons (zero weights, zero start value, zero output weights)
+    S.h2k = p == APEX_PREC_FP32 ? H2 : (H2 + 63) / 64 * 64;
     if (D->L == 3) {
-      S.w2 = b.take<uint8_t>((size_t)H2 * H1 * eb);
-      S.wo = b.take<uint8_t>((size_t)16 * H2 * (p == APEX_PREC_FP32 ? 4 : 2));
-      S.b2 = b.take<float>(H2);
+      S.w2 = b.take<uint8_t>((size_t)S.h2k * H1 * eb);
+      S.wo = b.take<uint8_t>(head_rows * S.h2k * (p == APEX_PREC_FP32 ? 4 : 2));
+      S.b2 = b.take<float>(S.h2k);
     } else {
       S.w2 = nullptr;
-      S.wo = b.take<uint8_t>((size_t)16 * H1 * eb);
+      S.wo = b.take<uint8_t>(head_rows * H1 * eb);
       S.b2 = nullptr;
     }
     S.bo = b.take<float>(kHeadsPad);
@@ -293,7 +298,7 @@ apex_status apex::engine_gather(apex_engine* E, int prec, const uint64_t* ids, u
   a.P = E->P;
   a.react = E->react;
   a.pd = S.dev;
-  a.H2 = E->H2;
+  a.H2 = E->prec[prec].h2k;
   a.ids = ids;
   a.n_ids = n;
   a.n_reactions = E->lib->T;
@@ -403,17 +408,24 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
     if (he == hipSuccess) he = launch_scales(S.amax, p, E->NL, S.scal, s);
     if (he == hipSuccess) {
       if (E->NL == 2) {
-        he = launch_frag_x(p, W2, E->H2, E->H1, E->H2 / 16, p == APEX_PREC_FP8 ? S.scal + 3 : nullptr, 1.0f,
-                           S.w2, s);
-        if (he == hipSuccess)
-          he = launch_frag_out_d(Wo, E->H, E->H2, p != APEX_PREC_FP32, 1.0f / E->c_act, S.wo, s);
-        if (he == hipSuccess) he = launch_bias(b2, E->H2, E->c_act, S.scal, bo, E->H, S.b2, S.bo, s);
+        if (p == APEX_PREC_FP32) {
+          he = launch_frag_x(p, W2, E->H2, E->H1, E->H2 / 16, nullptr, 1.0f, S.w2, s);
+          if (he == hipSuccess) he = launch_frag_out_d(Wo, E->H, E->H2, 0, 1.0f / E->c_act, S.wo, s);
+        } else {
+          he = launch_frag_x32(p, W2, E->H2, E->H1, S.h2k / 32, p == APEX_PREC_FP8 ? S.scal + 3 : nullptr, 1.0f,
+                               S.w2, s);
+          if (he == hipSuccess) he = launch_frag_out32(Wo, E->H, E->H2, S.h2k, 1.0f / E->c_act, S.wo, s);
+        }
+        if (he == hipSuccess) he = launch_bias(b2, E->H2, S.h2k, E->c_act, S.scal, bo, E->H, S.b2, S.bo, s);
       } else if (E->NL == 1) {
-        he = launch_frag_x(p, Wo, E->H, E->H1, 1, p == APEX_PREC_FP8 ? S.scal + 4 : nullptr, 1.0f / E->c_act,
-                           S.wo, s);
-        if (he == hipSuccess) he = launch_bias(nullptr, 0, E->c_act, S.scal, bo, E->H, nullptr, S.bo, s);
+        if (p == APEX_PREC_FP32)
+          he = launch_frag_x(p, Wo, E->H, E->H1, 1, nullptr, 1.0f / E->c_act, S.wo, s);
+        else
+          he = launch_frag_x32(p, Wo, E->H, E->H1, 1, p == APEX_PREC_FP8 ? S.scal + 4 : nullptr, 1.0f / E->c_act,
+                               S.wo, s);
+        if (he == hipSuccess) he = launch_bias(nullptr, 0, 0, E->c_act, S.scal, bo, E->H, nullptr, S.bo, s);
       } else {  // linear decoder: its bias is already in the slot-0 rows
-        he = launch_bias(nullptr, 0, 1.0f, S.scal, nullptr, 0, nullptr, S.bo, s);
+        he = launch_bias(nullptr, 0, 0, 1.0f, S.scal, nullptr, 0, nullptr, S.bo, s);
       }
     }
     if (he != hipSuccess) return fail(set_error(APEX_E_DEVICE, "weight preparation: %s", hipGetErrorString(he)));
@@ -426,8 +438,8 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
     std::vector<SelDev> plan;
     build_plan(lib, p, all, plan, &S.full_tiles, &S.full_compounds);
     he = up(S.plan, plan.data(), sizeof(SelDev) * plan.size());
-    if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, false, E->H2, &S.wg_per_cu);
-    if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, true, E->H2, nullptr);
+    if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, false, S.h2k, &S.wg_per_cu);
+    if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, true, S.h2k, nullptr);
     if (he != hipSuccess) return fail(set_error(APEX_E_DEVICE, "kernel setup: %s", hipGetErrorString(he)));
     if (S.wg_per_cu < 1) return fail(set_error(APEX_E_UNSUPPORTED, "fused kernel does not fit on a CU"));
   }

@@ -28,6 +28,7 @@ struct apex_decoder {
 namespace apex {
 
 struct PrecState {
+  uint32_t h2k = 0;  // second hidden width as the kernel runs it (BF16/FP8: padded to 64, zero neurons)
   bool on = false;
   void* w2 = nullptr;
   void* wo = nullptr;
@@ -48,7 +49,7 @@ struct PrecState {
 
 struct apex_engine {
   apex_library* lib = nullptr;
-  uint32_t H1 = 0, H2 = 0, NL = 0, H = 0, act = 0;
+  uint32_t H1 = 0, H2 = 0, NL = 0, H = 0, act = 0;  // H2: the decoder's second hidden width
   float c_act = 1.0f;
   std::vector<uint32_t> dims;
   uint32_t mask = 0, user_mask = 0;

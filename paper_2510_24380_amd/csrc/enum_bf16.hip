@@ -1,9 +1,9 @@
-// Instantiations of the fused enumeration kernel for APEX_PREC_BF16.
-#include "enum_kernel.h"
+// Instantiations of the 32x32-MFMA fused enumeration kernel for APEX_PREC_BF16.
+#include "enum32_kernel.h"
 
 namespace apex {
 
-#define APEX_K(H1, NL, ACT, G) reinterpret_cast<const void*>(&k_enum<APEX_PREC_BF16, H1, NL, ACT, G>)
+#define APEX_K(H1, NL, ACT, G) reinterpret_cast<const void*>(&k_enum32<APEX_PREC_BF16, H1, NL, ACT, G>)
 #define APEX_ACTS(H1, NL, G) \
   if (act == APEX_ACT_NONE) return APEX_K(H1, NL, APEX_ACT_NONE, G); \
   if (act == APEX_ACT_RELU) return APEX_K(H1, NL, APEX_ACT_RELU, G); \

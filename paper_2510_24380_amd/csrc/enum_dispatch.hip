@@ -1,5 +1,5 @@
 // Selection and launch of the fused enumeration kernel instantiations.
-#include "enum_kernel.h"
+#include "enum32_kernel.h"
 #include "launch.h"
 
 namespace apex {
@@ -17,10 +17,14 @@ static const void* enum_kernel(int prec, int h1, int nl, int act, bool gather) {
 
 int enum_rows_per_block_wave(int prec) { return enum_rows(prec); }
 
+static int lds_bytes(int prec, int h1, int nl, int h2, bool gather) {
+  return prec == APEX_PREC_FP32 ? enum_lds_bytes(prec, h1, nl, h2, gather) : enum32_lds_bytes(prec, h1, nl, h2, gather);
+}
+
 hipError_t enum_prepare(int prec, int h1, int nl, int act, bool gather, uint32_t h2, int* max_wg_per_cu) {
   const void* k = enum_kernel(prec, h1, nl, act, gather);
   if (!k) return hipErrorInvalidValue;
-  const int lds = enum_lds_bytes(prec, h1, nl, (int)h2, gather);
+  const int lds = lds_bytes(prec, h1, nl, (int)h2, gather);
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
   if (max_wg_per_cu) {
@@ -36,7 +40,7 @@ hipError_t launch_enum(int prec, int h1, int nl, int act, bool gather, const Enu
                        hipStream_t s) {
   const void* k = enum_kernel(prec, h1, nl, act, gather);
   if (!k) return hipErrorInvalidValue;
-  const int lds = enum_lds_bytes(prec, h1, nl, (int)a.H2, gather);
+  const int lds = lds_bytes(prec, h1, nl, (int)a.H2, gather);
   void* args[] = {const_cast<EnumArgs*>(&a)};
   return hipLaunchKernel(k, dim3(grid), dim3(enum_waves(prec) * 64), args, (size_t)lds, s);
 }

@@ -198,12 +198,50 @@ __global__ void k_frag_out_d(const float* __restrict__ Wo, uint32_t H, uint32_t 
   }
 }
 
-// GEMM accumulator start values c * b2 / S2, and the padded final bias.
-__global__ void k_bias(const float* __restrict__ b2, uint32_t h2, float c, const float* __restrict__ scal,
+// Operand fragments for the 32x32 kernel (BF16, FP8): A fragment (c, s, lane, e)
+// holds W[32 c + lane % 32][h n_in/2 + s E + e] * mul, h = lane / 32 (rows at or
+// beyond n_out are zero).
+template <int PREC>
+__global__ void k_frag_x32(const float* __restrict__ W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
+                           const float* __restrict__ mul_dev, float mul, void* __restrict__ out) {
+  constexpr uint32_t E = PREC == APEX_PREC_BF16 ? 8 : 32;
+  const uint32_t ns = n_in / (2 * E);
+  const uint64_t total = (uint64_t)n_chunks * ns * 64 * E;
+  const float m = mul * (mul_dev ? *mul_dev : 1.0f);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = i % E;
+    const uint32_t lane = (i / E) % 64;
+    const uint32_t s = (i / ((uint64_t)E * 64)) % ns;
+    const uint32_t c = (uint32_t)(i / ((uint64_t)E * 64 * ns));
+    const uint32_t row = 32 * c + lane % 32;
+    const uint32_t k = (lane / 32) * (n_in / 2) + s * E + e;
+    const float v = row < n_out ? W[(uint64_t)row * n_in + k] * m : 0.0f;
+    store_elem<PREC>(out, i, v);
+  }
+}
+
+// Final-layer fragments (BF16) of the 32x32 kernel, whose input is the GEMM
+// output in the 32x32 D layout: fragment (c, st, lane, e) holds
+// Wo[lane % 32][32 c + d32_row(8 st + e, lane / 32)] * mul (zero for padding heads).
+__global__ void k_frag_out32(const float* __restrict__ Wo, uint32_t H, uint32_t h2, uint32_t h2k, float mul,
+                             __bf16* __restrict__ out) {
+  const uint32_t total = 32 * h2k;  // (h2k / 32) chunks x 2 steps x 64 lanes x 8; neurons >= h2 are zero
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const uint32_t e = i % 8, lane = (i / 8) % 64, st = (i / 512) % 2, c = i / 1024;
+    const uint32_t head = lane % 32, hh = lane / 32;
+    const uint32_t v = 8 * st + e;
+    const uint32_t neuron = 32 * c + 8 * (v >> 2) + 4 * hh + (v & 3);
+    out[i] = (__bf16)(head < H && neuron < h2 ? Wo[(uint64_t)head * h2 + neuron] * mul : 0.0f);
+  }
+}
+
+// GEMM accumulator start values c * b2 / S2 (zero for padding neurons h2 ..
+// h2k - 1), and the padded final bias.
+__global__ void k_bias(const float* __restrict__ b2, uint32_t h2, uint32_t h2k, float c, const float* __restrict__ scal,
                        const float* __restrict__ bo, uint32_t H, float* __restrict__ b2_out,
                        float* __restrict__ bo_out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b2 && i < h2) b2_out[i] = c * b2[i] / scal[0];
+  if (b2 && i < h2k) b2_out[i] = i < h2 ? c * b2[i] / scal[0] : 0.0f;
   if (i < kHeadsPad) bo_out[i] = i < H ? bo[i] : 0.0f;
 }
 
@@ -673,16 +711,35 @@ hipError_t launch_frag_x(int prec, const float* W, uint32_t n_out, uint32_t n_in
   return hipGetLastError();
 }
 
+hipError_t launch_frag_x32(int prec, const float* W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
+                           const float* mul_dev, float mul, void* out, hipStream_t s) {
+  dim3 grid(256), block(256);
+  if (prec == APEX_PREC_BF16)
+    hipLaunchKernelGGL(k_frag_x32<APEX_PREC_BF16>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
+  else if (prec == APEX_PREC_FP8)
+    hipLaunchKernelGGL(k_frag_x32<APEX_PREC_FP8>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_frag_out32(const float* Wo, uint32_t H, uint32_t h2, uint32_t h2k, float mul, void* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_frag_out32, dim3(64), dim3(256), 0, s, Wo, H, h2, h2k, mul, reinterpret_cast<__bf16*>(out));
+  return hipGetLastError();
+}
+
 hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, int bf16, float mul, void* out,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_frag_out_d, dim3(64), dim3(256), 0, s, Wo, H, h2, bf16, mul, out);
   return hipGetLastError();
 }
 
-hipError_t launch_bias(const float* b2, uint32_t h2, float c, const float* scal, const float* bo, uint32_t H,
-                       float* b2_out, float* bo_out, hipStream_t s) {
-  const uint32_t n = h2 > kHeadsPad ? h2 : kHeadsPad;
-  hipLaunchKernelGGL(k_bias, dim3((n + 255) / 256), dim3(256), 0, s, b2, h2, c, scal, bo, H, b2_out, bo_out);
+hipError_t launch_bias(const float* b2, uint32_t h2, uint32_t h2k, float c, const float* scal, const float* bo,
+                       uint32_t H, float* b2_out, float* bo_out, hipStream_t s) {
+  if (h2k < h2) h2k = h2;
+  const uint32_t n = h2k > kHeadsPad ? h2k : kHeadsPad;
+  hipLaunchKernelGGL(k_bias, dim3((n + 255) / 256), dim3(256), 0, s, b2, h2, h2k, c, scal, bo, H, b2_out, bo_out);
   return hipGetLastError();
 }
 

@@ -244,7 +244,7 @@ apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t
   a.sel = plan_dev;
   a.n_sel = n_sel;
   a.pd = PS.dev;
-  a.H2 = E->H2;
+  a.H2 = E->prec[prec].h2k;
   a.n_queries = nq;
   a.queries = qd_dev;
   a.n_reactions = E->lib->T;

@@ -1,12 +1,14 @@
-// Lane-layout probe of the 16x16 MFMA builtins and conversions the engine uses.
+// Lane-layout probe of the MFMA builtins and conversions the engine uses.
 // Each kernel runs one wave: lane l reads its A and B operand registers from
-// a[l], b[l] and writes its four accumulator registers to d[4 l .. 4 l + 3].
+// a[l], b[l] and writes its accumulator registers to d[NV l .. NV l + NV - 1]
+// (NV = 4 for the 16x16 shapes, 16 for the 32x32 shapes).
 // Used only by the layout test; not part of the engine.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8;
 typedef __attribute__((__vector_size__(2 * sizeof(short)))) short s16x2;
 
@@ -28,6 +30,18 @@ __global__ void k_fp8(const i32x8* a, const i32x8* b, float* d) {
   c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[l], b[l], c, 0, 0, 0, 0, 0, 0);
   for (int v = 0; v < 4; ++v) d[4 * l + v] = c[v];
 }
+__global__ void k_bf16_32(const bf16x8* a, const bf16x8* b, float* d) {
+  const int l = threadIdx.x;
+  f32x16 c = {};
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[l], b[l], c, 0, 0, 0);
+  for (int v = 0; v < 16; ++v) d[16 * l + v] = c[v];
+}
+__global__ void k_fp8_32(const i32x8* a, const i32x8* b, float* d) {
+  const int l = threadIdx.x;
+  f32x16 c = {};
+  c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[l], b[l], c, 0, 0, 0, 0, 0, 0);
+  for (int v = 0; v < 16; ++v) d[16 * l + v] = c[v];
+}
 // x[i] -> E4M3 byte with power-of-two scale xs (divides), and -> bf16 bits
 __global__ void k_cvt(const float* x, int n, float xs, uint8_t* f8, uint16_t* bf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -44,7 +58,10 @@ __global__ void k_cvt(const float* x, int n, float xs, uint8_t* f8, uint16_t* bf
 extern "C" int probe_mfma(int kind, const void* a, const void* b, float* d) {
   if (kind == 0) hipLaunchKernelGGL(k_f32, dim3(1), dim3(64), 0, 0, (const float*)a, (const float*)b, d);
   else if (kind == 1) hipLaunchKernelGGL(k_bf16, dim3(1), dim3(64), 0, 0, (const bf16x8*)a, (const bf16x8*)b, d);
-  else hipLaunchKernelGGL(k_fp8, dim3(1), dim3(64), 0, 0, (const i32x8*)a, (const i32x8*)b, d);
+  else if (kind == 2) hipLaunchKernelGGL(k_fp8, dim3(1), dim3(64), 0, 0, (const i32x8*)a, (const i32x8*)b, d);
+  else if (kind == 3) hipLaunchKernelGGL(k_bf16_32, dim3(1), dim3(64), 0, 0, (const bf16x8*)a, (const bf16x8*)b, d);
+  else if (kind == 4) hipLaunchKernelGGL(k_fp8_32, dim3(1), dim3(64), 0, 0, (const i32x8*)a, (const i32x8*)b, d);
+  else return -1;
   return (int)hipDeviceSynchronize();
 }
 extern "C" int probe_cvt(const float* x, int n, float xs, uint8_t* f8, uint16_t* bf) {

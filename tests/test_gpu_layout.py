@@ -50,6 +50,21 @@ def run(probe, kind, a_regs, b_regs):
     return D
 
 
+def run32(probe, kind, a_regs, b_regs):
+    """32x32 shapes: lane l holds accumulator v at row 8 (v // 4) + 4 (l // 32) + v % 4,
+    column l % 32."""
+    a = torch.from_numpy(np.ascontiguousarray(a_regs)).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(b_regs)).cuda()
+    d = torch.zeros(64 * 16, dtype=torch.float32, device="cuda")
+    assert probe.probe_mfma(kind, a.data_ptr(), b.data_ptr(), d.data_ptr()) == 0
+    regs = d.cpu().numpy().reshape(64, 16)
+    D = np.zeros((32, 32))
+    for l in range(64):
+        for v in range(16):
+            D[8 * (v // 4) + 4 * (l // 32) + v % 4, l % 32] = regs[l, v]
+    return D, regs
+
+
 def test_mfma_f32_16x16x4(probe):
     rng = np.random.default_rng(1)
     A = rng.standard_normal((16, 4)).astype(np.float32)
@@ -76,6 +91,48 @@ def test_mfma_bf16_16x16x32(probe):
             b[l, e] = B[k, l % 16].view(np.uint32) >> 16
     D = run(probe, 1, a, b)
     np.testing.assert_allclose(D, A.astype(np.float64) @ B, rtol=1e-5, atol=1e-4)
+
+
+def test_mfma_bf16_32x32x16(probe):
+    """A: lane l holds row l % 32, k = 8 (l // 32) + e; B: column l % 32, same k."""
+    rng = np.random.default_rng(5)
+    def bf16_round(x):
+        u = x.astype(np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+        return u.view(np.float32)
+    A = bf16_round(rng.standard_normal((32, 16)))
+    B = bf16_round(rng.standard_normal((16, 32)))
+    a = np.zeros((64, 8), np.uint16)
+    b = np.zeros((64, 8), np.uint16)
+    for l in range(64):
+        for e in range(8):
+            k = 8 * (l // 32) + e
+            a[l, e] = A[l % 32, k].view(np.uint32) >> 16
+            b[l, e] = B[k, l % 32].view(np.uint32) >> 16
+    D, regs = run32(probe, 3, a, b)
+    if not np.allclose(D, A.astype(np.float64) @ B, rtol=1e-5, atol=1e-4):
+        print("lane 0 regs", regs[0], "lane 32 regs", regs[32])
+    np.testing.assert_allclose(D, A.astype(np.float64) @ B, rtol=1e-5, atol=1e-4)
+
+
+def test_mfma_fp8_32x32x64(probe):
+    """A: lane l holds row l % 32, k = 32 (l // 32) + e; B: column l % 32, same k."""
+    rng = np.random.default_rng(6)
+    tab = e4m3_table()
+    okn = np.where(np.isfinite(tab) & (np.abs(tab) <= 8) & (np.abs(tab) >= 2.0 ** -6))[0]
+    ca = rng.choice(okn, (32, 64)).astype(np.uint8)
+    cb = rng.choice(okn, (64, 32)).astype(np.uint8)
+    A, B = tab[ca], tab[cb]
+    a = np.zeros((64, 32), np.uint8)
+    b = np.zeros((64, 32), np.uint8)
+    for l in range(64):
+        for e in range(32):
+            k = 32 * (l // 32) + e
+            a[l, e] = ca[l % 32, k]
+            b[l, e] = cb[k, l % 32]
+    D, regs = run32(probe, 4, a, b)
+    e_norm = float(np.max(np.abs(D - A @ B) / (np.abs(A) @ np.abs(B))))
+    print(f"fp8 32x32x64 mfma, normal inputs: max error / sum|ab| {e_norm:.2e}")
+    assert e_norm < 2e-3
 
 
 def test_mfma_fp8_16x16x128(probe):
