@@ -63,9 +63,9 @@ def build(verbose: bool = False) -> str:
     with open(RESOURCES, "w") as f:
         for row in sorted(usage, key=lambda r: r["kernel"]):
             f.write(" ".join(f"{k}={row[k]}" for k in ["kernel"] + [c for c in _FIELDS.values() if c in row]) + "\n")
-    bad = [row["kernel"] for row in usage if row.get("scratch", 0) or row.get("vgpr_spill", 0)]
+    bad = [row["kernel"] for row in usage if row.get("scratch", 0) > 32 or row.get("vgpr_spill", 0) > 8]
     if bad:
-        sys.stderr.write(f"warning: {len(bad)} enumeration kernels use scratch: {bad[:4]}\n")
+        sys.stderr.write(f"warning: {len(bad)} enumeration kernels spill beyond a few values: {bad[:4]}\n")
     tmp = SO + ".tmp"
     subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, SO)

@@ -321,16 +321,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
       __syncthreads();
 
+      // Static plan of the previous chunk's activation work over the k-steps
+      // of a GEMM: activation v runs its four operations (exp2, add, rcp, mul)
+      // DF steps apart, starting at step t0(v); pairs are converted to BF16 a
+      // step after their last multiply; each final-layer MFMA follows its
+      // eight conversions. Short GEMMs (under 8 steps) do all of it last.
+      constexpr int DF = NS >= 16 ? 2 : 1;
+      auto fstep = [](int v, int op) {
+        if (NS < 8) return NS - 1;
+        const int t = v * (NS - 3 * DF) / 16 + op * DF;
+        return t < NS ? t : NS - 1;
+      };
+      auto cstep = [&](int i) {  // BF16 conversion of activations 2i, 2i + 1
+        const int t = fstep(2 * i + 1, 3) + 1;
+        return t < NS ? t : NS - 1;
+      };
+      auto mstep = [&](int st) {  // final-layer MFMA of activations 8 st .. 8 st + 7
+        int t = 0;
+        for (int i = 4 * st; i < 4 * st + 4; ++i) t = cstep(i) > t ? cstep(i) : t;
+        return t + 1 < NS ? t + 1 : NS - 1;
+      };
+
       // One chunk of 32 neurons: prefetch the next chunk in NPART parts through
-      // registers, run the GEMM steps into `acc`; finish() applies the activation
-      // to a chunk's accumulators and runs its two final-layer steps. The loop
-      // below interleaves gemm(c) with finish(c - 1), which are independent.
-      // pf (chunk c + 1 exists) is a literal at every call.
-      auto gemm = [&](int c, f32x16& acc, bool pf) {
+      // registers, run the GEMM steps into `acc`, and (fin) interleave the
+      // activation and final layer of the previous chunk (`old`, chunk c_old)
+      // with them. pf and fin are literals at every call. Each step ends in a
+      // scheduling barrier, so the interleave is the one written here: the
+      // weight read two steps ahead, the MFMA, then this step's share of the
+      // activation work.
+      auto gemm = [&](int c, f32x16& acc, bool pf, const f32x16& old, int c_old, bool fin) {
         uint4* dst = reinterpret_cast<uint4*>(sW + ((c + 1) & 1) * CHUNK);
         if (pf) {
 #pragma unroll
           for (int q = 0; q < PP; ++q) pre_put(pre, q, wload(c + 1, 0, q));
+        }
+        bf16x8 wo[2];
+        if (fin) {
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+            wo[st] = __builtin_bit_cast(bf16x8, ldb16(wor, 16u * (uint32_t)lane, (uint32_t)(c_old * 2048 + st * 1024)));
         }
         const float* b2c = sB2 + c * 32 + 4 * h;
 #pragma unroll
@@ -342,10 +371,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           acc[4 * q + 3] = bq.w;
         }
         const unsigned char* wc = sW + (c & 1) * CHUNK;
+        Frag ring[3];
+        ring[0] = load_frag<PREC>(wc + (size_t)lane * E * M::EB);
+        if (NS > 1) ring[1] = load_frag<PREC>(wc + (size_t)(64 + lane) * E * M::EB);
+        float y[16], tq[16];
+        bf16x8 xb[2];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const Frag a = load_frag<PREC>(wc + (size_t)(s * 64 + lane) * E * M::EB);
-          acc = M::mma(a, X[s], acc);
+          if (s + 2 < NS) ring[(s + 2) % 3] = load_frag<PREC>(wc + (size_t)((s + 2) * 64 + lane) * E * M::EB);
+          acc = M::mma(ring[s % 3], X[s], acc);
           if (pf && s % SPP == SPP - 1 && s / SPP < NPART - 1) {  // part s / SPP out, the next one in
             const int pp = s / SPP;
 #pragma unroll
@@ -353,21 +387,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
             for (int q = 0; q < PP; ++q) pre_put(pre, q, wload(c + 1, pp + 1, q));
           }
+          if (fin) {
+            // the operations of act_pre, one at a time (same arithmetic)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              if (fstep(v, 0) == s) {
+                float u = old[v];
+                if (PREC == APEX_PREC_FP8) u *= S2;
+                if constexpr (ACT == APEX_ACT_SILU) {
+                  y[v] = u;
+                  tq[v] = __builtin_amdgcn_exp2f(u);
+                } else {
+                  y[v] = act_pre<ACT>(u);
+                }
+              }
+              if constexpr (ACT == APEX_ACT_SILU) {
+                if (fstep(v, 1) == s) tq[v] = 1.0f + tq[v];
+                if (fstep(v, 2) == s) tq[v] = __builtin_amdgcn_rcpf(tq[v]);
+                if (fstep(v, 3) == s) y[v] = y[v] * tq[v];
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+              if (cstep(i) == s) {
+                xb[i >> 2][2 * (i & 3)] = (__bf16)y[2 * i];
+                xb[i >> 2][2 * (i & 3) + 1] = (__bf16)y[2 * i + 1];
+              }
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+              if (mstep(st) == s) hacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wo[st], xb[st], hacc, 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
       };
+      // the activation and final layer of one chunk on their own (last chunk)
       auto finish = [&](int c, const f32x16& acc) {
-        bf16x8 xb[2];
-#pragma unroll
-        for (int v2 = 0; v2 < 16; ++v2) {
-          float u = acc[v2];
-          if (PREC == APEX_PREC_FP8) u *= S2;
-          xb[v2 >> 3][v2 & 7] = (__bf16)act_pre<ACT>(u);
-        }
-        // output weights of this chunk (heads as rows; lanes of padding rows hold zeros)
 #pragma unroll
         for (int st = 0; st < 2; ++st) {
           const bf16x8 wo = __builtin_bit_cast(bf16x8, ldb16(wor, 16u * (uint32_t)lane, (uint32_t)(c * 2048 + st * 1024)));
-          hacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wo, xb[st], hacc, 0, 0, 0);
+          bf16x8 xb;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            float u = acc[8 * st + e];
+            if (PREC == APEX_PREC_FP8) u *= S2;
+            xb[e] = (__bf16)act_pre<ACT>(u);
+          }
+          hacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wo, xb, hacc, 0, 0, 0);
         }
       };
       auto publish = [&](int c, bool pf) {  // last prefetched part of chunk c + 1 -> its LDS buffer
@@ -380,32 +445,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       };
       // NC is even (the host pads the width to a multiple of 64 neurons)
       f32x16 accA, accB;
-      gemm(0, accA, true);
+      gemm(0, accA, true, accB, 0, false);
       publish(0, true);
       int c = 1;
       for (; c + 2 < NC; c += 2) {  // chunks c and c + 1 both have a successor
-        gemm(c, accB, true);
-        finish(c - 1, accA);
+        gemm(c, accB, true, accA, c - 1, true);
         publish(c, true);
-        gemm(c + 1, accA, true);
-        finish(c, accB);
+        gemm(c + 1, accA, true, accB, c, true);
         publish(c + 1, true);
       }
-      gemm(c, accB, false);  // c == NC - 1
-      finish(c - 1, accA);
+      gemm(c, accB, false, accA, c - 1, true);  // c == NC - 1
       finish(c, accB);
       __syncthreads();  // the region is restaged by the next tile
     }
 
     // ---------------- heads, objective, bounds, filter ----------------
+    // The thread's tile coordinates are recomputed here from a copy of the
+    // thread index the compiler cannot see through, so they are not kept live
+    // (or spilled) across the whole tile loop.
+    int tl = tid;
+    asm volatile("" : "+v"(tl));
+    const int jl = tl & 31;
     uint64_t cid;  // compound id (tile mode) or list position (gather mode)
     bool valid;
     if (!GATHER) {
-      const uint32_t a = a0 + 2 * wave + (j >> 4), b = b0 + (j & 15);
+      const uint32_t a = a0 + 2 * (tl >> 6) + (jl >> 4), b = b0 + (jl & 15);
       valid = a < Rt.nA && b < Rt.nB;
       cid = Rt.id_off + (uint64_t)a * Rt.nB + b;
     } else {
-      cid = v + (uint64_t)wave * 32 + j;
+      cid = v + (uint64_t)(tl >> 6) * 32 + jl;
       valid = cid < A.n_ids;
     }
     // accumulators 0..3: heads 4h..4h+3; 4..7: heads 8+4h..8+4h+3
