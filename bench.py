@@ -28,16 +28,27 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}  # dense MFMA, MI355X
 METRIC = "compounds/s scored+top-k, BF16/FP8 vs FP32 @ recall@k>=0.99; p99 query latency"
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_2510_24380_amd/csrc/enum_kernel.h", "paper_2510_24380_amd/csrc/apex_internal.h",
-                  "paper_2510_24380_amd/csrc/enum_{prec}.hip"]
+CSRC = "paper_2510_24380_amd/csrc/"
+
+
+def fused_kernel(prec):
+    """Name and defining sources of the fused kernel of one precision: FP32 runs
+    the 16x16 MFMA kernel, BF16/FP8 the 32x32 one."""
+    name, header = ("k_enum", "enum_kernel.h") if prec == "fp32" else ("k_enum32", "enum32_kernel.h")
+    return name, [CSRC + header, CSRC + "enum_common.h", CSRC + "apex_internal.h", CSRC + f"enum_{prec}.hip"]
+
+
+def log(msg):
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sources_sha256(prec):
     """Hash of the sources that define the fused kernel of one precision."""
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, rel.format(prec=prec)), "rb").read())
+    for rel in fused_kernel(prec)[1]:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
     return h.hexdigest()
 
 
@@ -45,7 +56,7 @@ def measured_traffic(prec, workload="c1"):
     """HBM bytes per launch of the fused kernel from the committed hardware-counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
     None when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(PROFILES, f"k_enum_{prec}_{workload}_counters.md")
+    path = os.path.join(PROFILES, f"{fused_kernel(prec)[0]}_{prec}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -223,7 +234,7 @@ def main_c3(args):
                    "n_compounds": n, "k": q.k, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision], "traffic": None,
-                     "kernel": "apex::k_enum (fused)", "avg_launch_ms": ms / max(launches, 1),
+                     "kernel": f"apex::{fused_kernel(args.precision)[0]} (fused)", "avg_launch_ms": ms / max(launches, 1),
                      "launches_per_step": launches / args.steps, "flops_per_compound": flops_c},
         "results": {"n_found": len(r.ids), "candidates": r.n_candidates, "reruns": r.n_reruns,
                     "best_ids": [int(x) for x in r.ids[:5]]},
@@ -297,7 +308,7 @@ def main():
         achieved = flops_launch / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
         return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK[prec], "traffic": measured_traffic(prec), "traffic_unit": "bytes/launch",
-                "kernel": "apex::k_enum (fused)",
+                "kernel": f"apex::{fused_kernel(prec)[0]} (fused)",
                 "avg_launch_ms": avg_ms, "launches_per_step": launches / steps,
                 "compounds_per_launch": comps / max(launches, 1), "flops_per_compound": flops_c}
 
@@ -315,14 +326,17 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+    log(f"engine ready ({n} compounds); timing {args.precision}")
     head = run(args.precision, args.steps, args.warmup)
     roof = kernel_roofline(args.precision)
+    log(f"{args.precision}: {head['compounds_per_s']:.4g} compounds/s, {head['ms_per_step']:.3f} ms/step")
     others = {}
     if not args.quick:
         for p in ("fp32", "bf16", "fp8"):
             if p != args.precision:
                 others[p] = run(p, max(2, args.steps // 4), 1)
                 others[p]["roofline_frac"] = kernel_roofline(p)["frac"]
+                log(f"{p}: {others[p]['compounds_per_s']:.4g} compounds/s")
     out = {
         "metric": METRIC,
         "value": head["compounds_per_s"],
@@ -352,8 +366,10 @@ def main():
         out["speedup_vs_fp32"] = head["compounds_per_s"] / others["fp32"]["compounds_per_s"]
     if args.serve_queries and not args.quick:
         out["serving"] = serve_bench(eng, lib_h, args.serve_queries, args.serve_qps)
+        log("serving stream done")
         out["p99_latency_ms"] = out["serving"]["served"]["p99_latency_ms"]
     if not args.no_cpu_baseline and not args.quick:
+        log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(lib_h, dec_h, q)
     print(json.dumps(out), flush=True)
 

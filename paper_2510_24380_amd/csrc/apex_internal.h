@@ -16,8 +16,7 @@ constexpr uint32_t kSelectThreads = 1024;
 // (the last slot). FP32 (16x16 MFMA kernel): 8 waves of 16 compounds each (one
 // A-row, 16 B-rows). BF16 and FP8 (32x32 MFMA kernel): 4 waves of 32 compounds
 // each (two A-rows, 16 B-rows), small enough in LDS for two workgroups per CU.
-template <int PREC> struct TileShape;
-template <> struct TileShape<APEX_PREC_FP32> { static constexpr int W = 8, R = 1, TA = 8; };
+constexpr int kWaves16 = 8, kTileA16 = 8;  // FP32 kernel: 8 waves, one A-row each
 constexpr int kTileB = 16;
 
 inline int tile_ta(int) { return 8; }

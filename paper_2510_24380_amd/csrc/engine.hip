@@ -11,7 +11,6 @@
 #include <string>
 #include <vector>
 
-#include "enum_kernel.h"
 #include "engine_impl.h"
 #include "launch.h"
 
@@ -409,8 +408,8 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
     if (he == hipSuccess) {
       if (E->NL == 2) {
         if (p == APEX_PREC_FP32) {
-          he = launch_frag_x(p, W2, E->H2, E->H1, E->H2 / 16, nullptr, 1.0f, S.w2, s);
-          if (he == hipSuccess) he = launch_frag_out_d(Wo, E->H, E->H2, 0, 1.0f / E->c_act, S.wo, s);
+          he = launch_frag_x(W2, E->H2, E->H1, E->H2 / 16, 1.0f, S.w2, s);
+          if (he == hipSuccess) he = launch_frag_out_d(Wo, E->H, E->H2, 1.0f / E->c_act, S.wo, s);
         } else {
           he = launch_frag_x32(p, W2, E->H2, E->H1, S.h2k / 32, p == APEX_PREC_FP8 ? S.scal + 3 : nullptr, 1.0f,
                                S.w2, s);
@@ -419,7 +418,7 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
         if (he == hipSuccess) he = launch_bias(b2, E->H2, S.h2k, E->c_act, S.scal, bo, E->H, S.b2, S.bo, s);
       } else if (E->NL == 1) {
         if (p == APEX_PREC_FP32)
-          he = launch_frag_x(p, Wo, E->H, E->H1, 1, nullptr, 1.0f / E->c_act, S.wo, s);
+          he = launch_frag_x(Wo, E->H, E->H1, 1, 1.0f / E->c_act, S.wo, s);
         else
           he = launch_frag_x32(p, Wo, E->H, E->H1, 1, p == APEX_PREC_FP8 ? S.scal + 4 : nullptr, 1.0f / E->c_act,
                                S.wo, s);

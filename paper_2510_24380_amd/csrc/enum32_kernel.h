@@ -22,7 +22,7 @@
 // lanes. Lane halves hold heads {4h..4h+3} and {8+4h..8+4h+3} (accumulators
 // 0..7); accumulators 8..15 are padding rows.
 #pragma once
-#include "enum_kernel.h"
+#include "enum_common.h"
 
 namespace apex {
 
@@ -64,7 +64,7 @@ __host__ __device__ constexpr int enum32_lds_bytes(int prec, int h1, int nl, int
   int region = rows > chunk ? rows : chunk;
   int wo = nl == 1 ? 32 * h1 * eb : 0;
   int b2 = nl == 2 ? h2 * 4 : 0;
-  return region + wo + b2;
+  return region + wo + b2 + kHeadsPad * 4;  // + final bias
 }
 
 template <int PREC, int H1, int NL, int ACT, bool GATHER>
@@ -94,6 +94,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   unsigned char* sW = smem;  // GEMM weight chunks share the region with the staged rows
   unsigned char* sWo = smem + REGION;  // one-hidden-layer output weights
   float* sB2 = reinterpret_cast<float*>(smem + REGION);  // two-hidden-layer GEMM start values
+  // final bias, read from LDS in the epilogue (a global pointer to it would be
+  // hoisted out of the tile loop and held in registers)
+  float* sBo = reinterpret_cast<float*>(smem + REGION + (NL == 1 ? 32 * H1 * M::EB : 0)) + (NL == 2 ? A.H2 : 0);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, j = lane & 31;
   const uint32_t H2 = NL == 2 ? A.H2 : 0;
@@ -124,6 +127,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   {
     if (NL == 2)
       for (int i = tid; i < (int)H2; i += T) sB2[i] = A.pd.b2[i];
+    if (tid < kHeadsPad) sBo[tid] = A.pd.bo[tid];
     if (NL == 1) {
       const uint4* src = reinterpret_cast<const uint4*>(A.pd.wo);
       uint4* dst = reinterpret_cast<uint4*>(sWo);
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if constexpr (NL == 1) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const Frag wo = load_frag<PREC>(sWo + (size_t)(s * 64 + lane) * E * M::EB);
+        const Frag wo = load_frag<Frag>(sWo + (size_t)(s * 64 + lane) * E * M::EB);
         hacc = M::mma(wo, X[s], hacc);
       }
     } else {
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       // DF steps apart, starting at step t0(v); pairs are converted to BF16 a
       // step after their last multiply; each final-layer MFMA follows its
       // eight conversions. Short GEMMs (under 8 steps) do all of it last.
-      constexpr int DF = NS >= 16 ? 2 : 1;
+      constexpr int DF = 1;
       auto fstep = [](int v, int op) {
         if (NS < 8) return NS - 1;
         const int t = v * (NS - 3 * DF) / 16 + op * DF;
@@ -372,13 +376,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
         const unsigned char* wc = sW + (c & 1) * CHUNK;
         Frag ring[3];
-        ring[0] = load_frag<PREC>(wc + (size_t)lane * E * M::EB);
-        if (NS > 1) ring[1] = load_frag<PREC>(wc + (size_t)(64 + lane) * E * M::EB);
+        ring[0] = load_frag<Frag>(wc + (size_t)lane * E * M::EB);
+        if (NS > 1) ring[1] = load_frag<Frag>(wc + (size_t)(64 + lane) * E * M::EB);
         float y[16], tq[16];
         bf16x8 xb[2];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          if (s + 2 < NS) ring[(s + 2) % 3] = load_frag<PREC>(wc + (size_t)((s + 2) * 64 + lane) * E * M::EB);
+          if (s + 2 < NS) ring[(s + 2) % 3] = load_frag<Frag>(wc + (size_t)((s + 2) * 64 + lane) * E * M::EB);
           acc = M::mma(ring[s % 3], X[s], acc);
           if (pf && s % SPP == SPP - 1 && s / SPP < NPART - 1) {  // part s / SPP out, the next one in
             const int pp = s / SPP;
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // accumulators 0..3: heads 4h..4h+3; 4..7: heads 8+4h..8+4h+3
     float hd[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) hd[q] = fmaf(hacc[q], So, A.pd.bo[d32_row(q, h)]);
+    for (int q = 0; q < 8; ++q) hd[q] = fmaf(hacc[q], So, sBo[d32_row(q, h)]);
 
     if constexpr (GATHER) {
       if (valid) {

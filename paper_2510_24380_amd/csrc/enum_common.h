@@ -1,0 +1,102 @@
+// Device helpers shared by the fused enumeration kernels (16x16 FP32 in
+// enum_kernel.h, 32x32 BF16/FP8 in enum32_kernel.h) and the scoring, selection
+// and lookup kernels: operand vector types, the prescaled activations, the
+// objective's summation order, the (objective, id) key order of the threshold
+// (eq. "apex_topk": larger objective first, smaller id on ties) and the
+// reaction / tile-plan lookups.
+#pragma once
+#include "apex_internal.h"
+
+namespace apex {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8;
+typedef __attribute__((__vector_size__(2 * sizeof(short)))) short s16x2;
+
+// Activation on prescaled inputs. For SiLU the hoisted tables and GEMM biases
+// carry a factor c = -log2(e): with h = c x, SiLU(x) * c = h / (1 + 2^h), one
+// exp2 and one reciprocal; the factor 1/c is folded into the next layer.
+template <int ACT>
+__device__ __forceinline__ float act_pre(float h) {
+  if constexpr (ACT == APEX_ACT_SILU) {
+    float e = __builtin_amdgcn_exp2f(h);
+    return h * __builtin_amdgcn_rcpf(1.0f + e);
+  } else if constexpr (ACT == APEX_ACT_RELU) {
+    return fmaxf(h, 0.0f);
+  } else {
+    return h;
+  }
+}
+
+// Objective of four heads, combined across groups of four in a fixed order by
+// the callers; every kernel that scores a compound uses the same order, so its
+// objective is the same bits in every kernel.
+__device__ __forceinline__ float obj_partial(const float* w4, const float* h4) {
+  float p = w4[0] * h4[0];
+  p = fmaf(w4[1], h4[1], p);
+  p = fmaf(w4[2], h4[2], p);
+  p = fmaf(w4[3], h4[3], p);
+  return p;
+}
+
+__device__ __forceinline__ float canon_zero(float o) { return o == 0.0f ? 0.0f : o; }
+
+// Order-preserving map of a float to uint32 (larger float -> larger key).
+__device__ __forceinline__ uint32_t ord_f32(float o) {
+  uint32_t u = __float_as_uint(o);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ bool key_passes(float o, uint64_t id, float tau_o, uint64_t tau_id) {
+  return o > tau_o || (o == tau_o && id <= tau_id);
+}
+
+// Conversion of activations into low-precision MFMA operand fragments, four
+// values at a time (element positions 4 q .. 4 q + 3 of the fragment).
+template <int PREC> struct Pack;
+template <> struct Pack<APEX_PREC_BF16> {
+  __device__ static inline void put4(bf16x8& f, int q, float a, float b, float c, float d, float) {
+    f[4 * q + 0] = (__bf16)a;
+    f[4 * q + 1] = (__bf16)b;
+    f[4 * q + 2] = (__bf16)c;
+    f[4 * q + 3] = (__bf16)d;
+  }
+};
+template <> struct Pack<APEX_PREC_FP8> {
+  // xs: power-of-two scale; the hardware conversion divides by it and rounds to
+  // nearest E4M3 (OCP, max 448). The engine picks xs from the library's exact
+  // activation range, so no value overflows.
+  __device__ static inline void put4(i32x8& f, int q, float a, float b, float c, float d, float xs) {
+    s16x2 v = {0, 0};
+    v = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(v, a, b, xs, false);
+    v = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(v, c, d, xs, true);
+    f[q] = __builtin_bit_cast(int, v);
+  }
+};
+
+template <typename F>
+__device__ __forceinline__ F load_frag(const unsigned char* p) {
+  return *reinterpret_cast<const F*>(p);
+}
+
+__device__ __forceinline__ uint32_t find_reaction(const ReactDev* react, uint32_t n, uint64_t id) {
+  uint32_t lo = 0, hi = n;  // last t with id_off <= id
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (react[mid].id_off <= id) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t find_sel(const SelDev* sel, uint32_t n, uint64_t v) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (sel[mid].tile_start <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace apex

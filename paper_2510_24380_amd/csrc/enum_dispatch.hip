@@ -1,4 +1,5 @@
 // Selection and launch of the fused enumeration kernel instantiations.
+#include "enum_kernel.h"
 #include "enum32_kernel.h"
 #include "launch.h"
 
@@ -18,7 +19,7 @@ static const void* enum_kernel(int prec, int h1, int nl, int act, bool gather) {
 int enum_rows_per_block_wave(int prec) { return enum_rows(prec); }
 
 static int lds_bytes(int prec, int h1, int nl, int h2, bool gather) {
-  return prec == APEX_PREC_FP32 ? enum_lds_bytes(prec, h1, nl, h2, gather) : enum32_lds_bytes(prec, h1, nl, h2, gather);
+  return prec == APEX_PREC_FP32 ? enum_lds_bytes(h1, nl, h2, gather) : enum32_lds_bytes(prec, h1, nl, h2, gather);
 }
 
 hipError_t enum_prepare(int prec, int h1, int nl, int act, bool gather, uint32_t h2, int* max_wg_per_cu) {

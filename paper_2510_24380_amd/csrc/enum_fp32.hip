@@ -3,7 +3,7 @@
 
 namespace apex {
 
-#define APEX_K(H1, NL, ACT, G) reinterpret_cast<const void*>(&k_enum<APEX_PREC_FP32, H1, NL, ACT, G>)
+#define APEX_K(H1, NL, ACT, G) reinterpret_cast<const void*>(&k_enum<H1, NL, ACT, G>)
 #define APEX_ACTS(H1, NL, G) \
   if (act == APEX_ACT_NONE) return APEX_K(H1, NL, APEX_ACT_NONE, G); \
   if (act == APEX_ACT_RELU) return APEX_K(H1, NL, APEX_ACT_RELU, G); \

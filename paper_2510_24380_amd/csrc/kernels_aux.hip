@@ -1,7 +1,7 @@
 // Engine-build kernels (hoist, scales, weight layouts) and the selection kernels
 // of the search: candidate scoring, radix select with compaction, rank sort,
 // id sampling and id decoding.
-#include "enum_kernel.h"
+#include "enum_common.h"
 #include "launch.h"
 
 namespace apex {
@@ -137,10 +137,37 @@ __global__ void k_scales(const float* __restrict__ amax, int prec, int nl, float
   scal[4] = iwo;
 }
 
-template <int PREC> __device__ inline void store_elem(void* base, uint64_t i, float v);
-template <> __device__ inline void store_elem<APEX_PREC_FP32>(void* base, uint64_t i, float v) {
-  reinterpret_cast<float*>(base)[i] = v;
+// FP32 operand fragments of a weight matrix W [n_out x n_in] (row-major) for a
+// layer whose input activations are in the 16x16 kernel's order: fragment
+// (c, s, lane) holds W[16 c + lane % 16][g n_in/4 + s] * mul, g = lane / 16.
+__global__ void k_frag_x(const float* __restrict__ W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks, float mul,
+                         float* __restrict__ out) {
+  const uint32_t ns = n_in / 4;
+  const uint64_t total = (uint64_t)n_chunks * ns * 64;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t lane = i % 64;
+    const uint32_t s = (i / 64) % ns;
+    const uint32_t c = (uint32_t)(i / (64ull * ns));
+    const uint32_t row = 16 * c + lane % 16;
+    const uint32_t k = (lane / 16) * (n_in / 4) + s;
+    out[i] = row < n_out ? W[(uint64_t)row * n_in + k] * mul : 0.0f;
+  }
 }
+
+// FP32 final-layer fragments when its input is the GEMM output in the 16x16 D
+// layout (lane group g holds neurons 4 g + v of every 16-neuron chunk): index
+// (c, v, lane) -> Wo[lane % 16][16 c + 4 g + v].
+__global__ void k_frag_out_d(const float* __restrict__ Wo, uint32_t H, uint32_t h2, float mul,
+                             float* __restrict__ out) {
+  const uint32_t total = 16 * h2;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const uint32_t lane = i % 64, v = (i / 64) % 4, c = i / 256;
+    const uint32_t head = lane % 16, neuron = 16 * c + 4 * (lane / 16) + v;
+    out[i] = head < H ? Wo[(uint64_t)head * h2 + neuron] * mul : 0.0f;
+  }
+}
+
+template <int PREC> __device__ inline void store_elem(void* base, uint64_t i, float v);
 template <> __device__ inline void store_elem<APEX_PREC_BF16>(void* base, uint64_t i, float v) {
   reinterpret_cast<__bf16*>(base)[i] = (__bf16)v;
 }
@@ -149,53 +176,6 @@ template <> __device__ inline void store_elem<APEX_PREC_FP8>(void* base, uint64_
   s16x2 p = {0, 0};
   p = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(p, v, 0.0f, 1.0f, false);
   reinterpret_cast<uint8_t*>(base)[i] = (uint8_t)(__builtin_bit_cast(uint32_t, p) & 0xffu);
-}
-
-// Operand fragments of a weight matrix W [n_out x n_in] (row-major) for a layer
-// whose input activations are in the kernel's X order: fragment (c, s, lane, e)
-// holds W[16 c + lane % 16][g n_in/4 + s E + e] * mul, g = lane / 16.
-template <int PREC>
-__global__ void k_frag_x(const float* __restrict__ W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
-                         const float* __restrict__ mul_dev, float mul, void* __restrict__ out) {
-  constexpr int E = MfmaT<PREC>::E;
-  const uint32_t ns = n_in / MfmaT<PREC>::KS;
-  const uint64_t total = (uint64_t)n_chunks * ns * 64 * E;
-  const float m = mul * (mul_dev ? *mul_dev : 1.0f);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t e = i % E;
-    const uint32_t lane = (i / E) % 64;
-    const uint32_t s = (i / ((uint64_t)E * 64)) % ns;
-    const uint32_t c = (uint32_t)(i / ((uint64_t)E * 64 * ns));
-    const uint32_t row = 16 * c + lane % 16;
-    const uint32_t k = (lane / 16) * (n_in / 4) + s * E + e;
-    const float v = row < n_out ? W[(uint64_t)row * n_in + k] * m : 0.0f;
-    store_elem<PREC>(out, i, v);
-  }
-}
-
-// Final-layer fragments when its input is the GEMM output in the 16x16 D layout
-// (lane group g holds neurons 4 g + v of every 16-neuron chunk).
-// fp32 (16x16x4): index (c, v, lane) -> Wo[lane % 16][16 c + 4 g + v].
-// bf16 (16x16x32, chunks in pairs p): (p, lane, e) -> Wo[lane % 16][32 p + 4 g + e]
-// for e < 4 and Wo[lane % 16][32 p + 16 + 4 g + e - 4] for e >= 4.
-__global__ void k_frag_out_d(const float* __restrict__ Wo, uint32_t H, uint32_t h2, int bf16, float mul,
-                             void* __restrict__ out) {
-  const uint32_t total = 16 * h2;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-    uint32_t head, neuron;
-    if (!bf16) {
-      const uint32_t lane = i % 64, v = (i / 64) % 4, c = i / 256;
-      head = lane % 16;
-      neuron = 16 * c + 4 * (lane / 16) + v;
-    } else {
-      const uint32_t e = i % 8, lane = (i / 8) % 64, p = i / 512;
-      head = lane % 16;
-      neuron = 32 * p + (e < 4 ? 4 * (lane / 16) + e : 16 + 4 * (lane / 16) + (e - 4));
-    }
-    const float v = head < H ? Wo[(uint64_t)head * h2 + neuron] * mul : 0.0f;
-    if (!bf16) reinterpret_cast<float*>(out)[i] = v;
-    else reinterpret_cast<__bf16*>(out)[i] = (__bf16)v;
-  }
 }
 
 // Operand fragments for the 32x32 kernel (BF16, FP8): A fragment (c, s, lane, e)
@@ -699,15 +679,10 @@ hipError_t launch_scales(const float* amax, int prec, int nl, float* scal, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_frag_x(int prec, const float* W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
-                         const float* mul_dev, float mul, void* out, hipStream_t s) {
-  dim3 grid(256), block(256);
-  if (prec == APEX_PREC_FP32)
-    hipLaunchKernelGGL(k_frag_x<APEX_PREC_FP32>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
-  else if (prec == APEX_PREC_BF16)
-    hipLaunchKernelGGL(k_frag_x<APEX_PREC_BF16>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
-  else
-    hipLaunchKernelGGL(k_frag_x<APEX_PREC_FP8>, grid, block, 0, s, W, n_out, n_in, n_chunks, mul_dev, mul, out);
+hipError_t launch_frag_x(const float* W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks, float mul, void* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_frag_x, dim3(256), dim3(256), 0, s, W, n_out, n_in, n_chunks, mul,
+                     reinterpret_cast<float*>(out));
   return hipGetLastError();
 }
 
@@ -729,12 +704,10 @@ hipError_t launch_frag_out32(const float* Wo, uint32_t H, uint32_t h2, uint32_t 
   return hipGetLastError();
 }
 
-hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, int bf16, float mul, void* out,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_frag_out_d, dim3(64), dim3(256), 0, s, Wo, H, h2, bf16, mul, out);
+hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, float mul, void* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_frag_out_d, dim3(64), dim3(256), 0, s, Wo, H, h2, mul, reinterpret_cast<float*>(out));
   return hipGetLastError();
 }
-
 hipError_t launch_bias(const float* b2, uint32_t h2, uint32_t h2k, float c, const float* scal, const float* bo,
                        uint32_t H, float* b2_out, float* bo_out, hipStream_t s) {
   if (h2k < h2) h2k = h2;

@@ -17,14 +17,13 @@ hipError_t launch_act_range(const float* P, uint32_t h1, const uint64_t* slot_ro
                             hipStream_t s);
 hipError_t launch_absmax(const float* x, uint64_t n, float* out, hipStream_t s);
 hipError_t launch_scales(const float* amax, int prec, int nl, float* scal, hipStream_t s);
-hipError_t launch_frag_x(int prec, const float* W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
-                         const float* mul_dev, float mul, void* out, hipStream_t s);
+hipError_t launch_frag_x(const float* W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks, float mul, void* out,
+                         hipStream_t s);
 hipError_t launch_frag_x32(int prec, const float* W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
                            const float* mul_dev, float mul, void* out, hipStream_t s);
 hipError_t launch_frag_out32(const float* Wo, uint32_t H, uint32_t h2, uint32_t h2k, float mul, void* out,
                              hipStream_t s);
-hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, int bf16, float mul, void* out,
-                             hipStream_t s);
+hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, float mul, void* out, hipStream_t s);
 hipError_t launch_bias(const float* b2, uint32_t h2, uint32_t h2k, float c, const float* scal, const float* bo,
                        uint32_t H, float* b2_out, float* bo_out, hipStream_t s);
 hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,

@@ -36,7 +36,9 @@ using namespace apex;
 
 namespace apex {
 
-constexpr uint64_t kFirstChunk = 1ull << 22;  // compounds in the first chunk
+// compounds in the first chunk: small, so that the appends before the first
+// select stay few even with the warm start's loose threshold
+constexpr uint64_t kFirstChunk = 1ull << 20;
 constexpr uint64_t kMaxChunk = 1ull << 27;
 
 // Test knobs, read from the environment at every search: APEX_TEST_CHUNK fixes
@@ -107,7 +109,9 @@ void query_sizes(const apex_query* q, QPlan& P) {
   const uint64_t forced = env_u64("APEX_TEST_CAP");
   if (forced) cap = std::max<uint64_t>(forced, 2ull * P.K);
   P.cap = (uint32_t)cap;
-  P.hwm = P.cap / 2;
+  // select as soon as 8 K candidates (at least 2^15) have gathered: selects of
+  // small buffers are cheap, and each one tightens the threshold for the rest
+  P.hwm = (uint32_t)std::min<uint64_t>(P.cap / 2, std::max<uint64_t>(8ull * P.K, 1ull << 15));
   P.cap2 = P.K;
 }
 
@@ -303,11 +307,15 @@ apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_
 }
 
 apex_status finish_query(apex_engine* E, const apex_query* q, const QPlan& P, const QueryDev* qd_dev,
-                         const QueryDev* qx_dev, hipStream_t s, apex_result* res) {
+                         const QueryDev* qx_dev, hipStream_t s, apex_result* res, const QState* st_known) {
   (void)q;
   QState st1{}, st2{};
-  HIP_TRY(hipMemcpyAsync(&st1, P.st, sizeof(QState), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  if (st_known) {
+    st1 = *st_known;
+  } else {
+    HIP_TRY(hipMemcpyAsync(&st1, P.st, sizeof(QState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   const uint32_t n1 = std::min(st1.count, P.K);
   uint32_t n_found = 0;
   if (!P.lowp) {
@@ -472,11 +480,14 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
 
   // re-runs of chunks whose appends overflowed a candidate buffer
   std::vector<uint32_t> flags((size_t)nq * sh.n_flags);
+  std::vector<QState> states(nq);  // read with the flags: final when no chunk needs a re-run
   uint32_t reruns = 0;
   for (int round = 0;; ++round) {
-    for (uint32_t i = 0; i < nq; ++i)
+    for (uint32_t i = 0; i < nq; ++i) {
       HIP_TRY(hipMemcpyAsync(flags.data() + (size_t)i * sh.n_flags, P[i].rerun, sizeof(uint32_t) * sh.n_flags,
                              hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(&states[i], P[i].st, sizeof(QState), hipMemcpyDeviceToHost, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     bool any = false;
     for (uint32_t f : flags) any |= f != 0;
@@ -509,7 +520,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
 
   // 3-4. answer of each query
   for (uint32_t i = 0; i < nq; ++i) {
-    apex_status st = finish_query(E, &qs[i], P[i], sh.qd + i, sh.qx + i, s, &res[i]);
+    apex_status st = finish_query(E, &qs[i], P[i], sh.qd + i, sh.qx + i, s, &res[i], &states[i]);
     if (st != APEX_OK) return st;
     res[i].n_scored = scored;
     res[i].n_reruns = reruns;

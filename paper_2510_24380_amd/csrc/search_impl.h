@@ -65,8 +65,11 @@ apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_
                        uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev, uint32_t nq,
                        hipStream_t s);
 // Answer of one query whose enumeration is complete (stage 3-4; synchronises s).
+// st_known: the query's threshold state as already read back after its last
+// select (saves a synchronisation), or nullptr.
 apex_status finish_query(apex_engine* E, const apex_query* q, const QPlan& P, const QueryDev* qd_dev,
-                         const QueryDev* qx_dev, hipStream_t s, apex_result* res);
+                         const QueryDev* qx_dev, hipStream_t s, apex_result* res,
+                         const QState* st_known = nullptr);
 // Resolves the engine's pending kernel timings (after a synchronisation).
 apex_status profile_collect(apex_engine* E);
 
