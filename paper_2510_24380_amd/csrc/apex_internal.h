@@ -69,6 +69,23 @@ struct QState {
   uint64_t appended;  // total appends over the search
 };
 
+// Selection scratch of one query (device): pivots placed from a sorted sample of
+// the candidate keys, exact counts above them, and the "bracket" - the entries
+// between the two pivots that enclose the K-th key - sorted in LDS.
+constexpr uint32_t kSelSample = 2048;
+constexpr uint32_t kSelBracket = 8192;
+constexpr int kSelPivots = 8;
+struct SelScratch {
+  uint32_t piv[kSelPivots];     // order keys, non-increasing
+  uint32_t cnt_gt[kSelPivots];  // entries with key > piv[j]
+  uint32_t cnt_ge[kSelPivots];  // entries with key >= piv[j]
+  uint32_t pos_sure, pos_br;    // compaction cursors
+  uint32_t mode;                // 0: pivot path, 1: one-workgroup radix path
+  uint32_t pad;
+  uint32_t br_key[kSelBracket];
+  uint64_t br_id[kSelBracket];
+};
+
 // Query parameters for the fused kernel and the scoring kernels.
 struct QueryDev {
   float w[kHeadsPad];
@@ -85,6 +102,7 @@ struct QueryDev {
   uint32_t K;            // entries kept (k, or the low-precision pool size)
   uint32_t hwm;          // compaction trigger
   uint32_t active;       // 0: skip this query in a pass
+  SelScratch* sel;       // selection scratch
 };
 
 struct EnumArgs {

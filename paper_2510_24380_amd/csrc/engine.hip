@@ -303,7 +303,7 @@ apex_status apex::engine_gather(apex_engine* E, int prec, const uint64_t* ids, u
   a.n_reactions = E->lib->T;
   a.n_total = E->lib->total;
   a.heads_out = heads;
-  const uint32_t per = enum_waves(prec) * enum_rows(prec) * 16;
+  const uint32_t per = gather_per_block(prec, (int)E->NL);
   const uint32_t grid = (n + per - 1) / per;
   HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, true, a, grid, s));
   return APEX_OK;

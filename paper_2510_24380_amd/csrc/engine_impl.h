@@ -1,6 +1,8 @@
 // Host-side handle types behind the opaque pointers of include/apex.h.
 #pragma once
 #include <atomic>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "apex_internal.h"
@@ -78,12 +80,17 @@ struct apex_engine {
   };
   std::vector<hipEvent_t> ev_free;
   std::vector<Timed> ev_pending;
+  // pinned host buffers for the per-search result readback, reused across
+  // searches (host memory; the library allocates no device memory)
+  std::mutex pin_mu;
+  std::vector<std::pair<void*, size_t>> pin_free;
   ~apex_engine() {
     for (auto e : ev_free) (void)hipEventDestroy(e);
     for (auto& t : ev_pending) {
       (void)hipEventDestroy(t.a);
       (void)hipEventDestroy(t.b);
     }
+    for (auto& b : pin_free) (void)hipHostFree(b.first);
   }
 };
 

@@ -8,17 +8,25 @@ namespace apex {
 const void* enum_kernel_fp32(int h1, int nl, int act, bool gather);
 const void* enum_kernel_bf16(int h1, int nl, int act, bool gather);
 const void* enum_kernel_fp8(int h1, int nl, int act, bool gather);
+const void* gather_split_fp32(int h1, int act);
+
+// FP32 gathers with two hidden layers use the split-chunk kernel
+static bool split_gather(int prec, int nl, bool gather) { return prec == APEX_PREC_FP32 && nl == 2 && gather; }
 
 static const void* enum_kernel(int prec, int h1, int nl, int act, bool gather) {
+  if (split_gather(prec, nl, gather)) return gather_split_fp32(h1, act);
   if (prec == APEX_PREC_FP32) return enum_kernel_fp32(h1, nl, act, gather);
   if (prec == APEX_PREC_BF16) return enum_kernel_bf16(h1, nl, act, gather);
   if (prec == APEX_PREC_FP8) return enum_kernel_fp8(h1, nl, act, gather);
   return nullptr;
 }
 
-int enum_rows_per_block_wave(int prec) { return enum_rows(prec); }
+uint32_t gather_per_block(int prec, int nl) {
+  return split_gather(prec, nl, true) ? 16u : (uint32_t)(enum_waves(prec) * enum_rows(prec) * 16);
+}
 
 static int lds_bytes(int prec, int h1, int nl, int h2, bool gather) {
+  if (split_gather(prec, nl, gather)) return gather_split_lds_bytes(h2);
   return prec == APEX_PREC_FP32 ? enum_lds_bytes(h1, nl, h2, gather) : enum32_lds_bytes(prec, h1, nl, h2, gather);
 }
 

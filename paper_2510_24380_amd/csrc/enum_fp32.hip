@@ -23,4 +23,19 @@ const void* enum_kernel_fp32(int h1, int nl, int act, bool gather) {
   return nullptr;
 }
 
+// Two-hidden-layer gathers of short lists (k_gather_split).
+const void* gather_split_fp32(int h1, int act) {
+#define APEX_G(H1) \
+  if (h1 == H1) { \
+    if (act == APEX_ACT_NONE) return reinterpret_cast<const void*>(&k_gather_split<H1, APEX_ACT_NONE>); \
+    if (act == APEX_ACT_RELU) return reinterpret_cast<const void*>(&k_gather_split<H1, APEX_ACT_RELU>); \
+    if (act == APEX_ACT_SILU) return reinterpret_cast<const void*>(&k_gather_split<H1, APEX_ACT_SILU>); \
+  }
+  APEX_G(128)
+  APEX_G(256)
+  APEX_G(512)
+#undef APEX_G
+  return nullptr;
+}
+
 }  // namespace apex

@@ -363,4 +363,119 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
   }
 }
 
+// Heads of listed compounds with a two-hidden-layer decoder, for short lists
+// (FP32 rescoring of a pool, answer heads). The tile kernel's gather mode
+// gives each wave all H2/16 weight chunks in sequence, which leaves a short
+// list with few, long-running workgroups. Here a workgroup takes 16 compounds,
+// every wave computes their layer-1 activations, wave w takes chunks w, w + 8,
+// ... (weights read from the caches), and the eight partial final-layer sums
+// are added in wave order.
+__host__ __device__ constexpr int gather_split_lds_bytes(int h2) { return 16 * h2 * 4 + h2 * 4 + kWaves16 * 64 * 16; }
+
+template <int H1, int ACT>
+__global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gather_split(
+    EnumArgs A) {
+  constexpr int W = kWaves16, T = W * 64;
+  constexpr int NS = H1 / 4, KG = H1 / 4;
+  constexpr int B = 16;  // weight fragments per batch of loads
+  static_assert(NS % B == 0, "layout");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const uint32_t H2 = A.H2;
+  float* sWo = reinterpret_cast<float*>(smem);
+  float* sB2 = sWo + 16 * H2;
+  f32x4* sRed = reinterpret_cast<f32x4*>(sB2 + H2);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+  const int NC = (int)(H2 / 16);
+  const uint64_t v = (uint64_t)blockIdx.x * 16;
+  if (v >= A.n_ids) return;  // uniform per workgroup
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(A.pd.wo);
+    uint4* dst = reinterpret_cast<uint4*>(sWo);
+    for (int i = tid; i < (int)(16 * H2 / 4); i += T) dst[i] = src[i];
+    for (int i = tid; i < (int)H2; i += T) sB2[i] = A.pd.b2[i];
+  }
+  // layer-1 activations of compound v + j
+  uint64_t item = v + j;
+  item = item < A.n_ids ? item : (uint64_t)A.n_ids - 1;
+  const uint64_t id = A.ids[item];
+  const ReactDev rr = A.react[find_reaction(A.react, (uint32_t)A.n_reactions, id)];
+  const uint64_t loc = id - rr.id_off;
+  // ids past the library end are clamped to rows in bounds (reported as NaN)
+  const uint64_t a64 = loc / rr.nB;
+  const uint32_t a = a64 < rr.nA ? (uint32_t)a64 : rr.nA - 1;
+  const uint32_t b = (uint32_t)(loc % rr.nB);
+  const float* pa;
+  const float* pa1 = nullptr;
+  if (rr.three) {
+    const uint32_t i0 = a / rr.n1, i1 = a - i0 * rr.n1;
+    pa = A.P + (uint64_t)(rr.row0 + i0) * H1 + g * KG;
+    pa1 = A.P + (uint64_t)(rr.row1 + i1) * H1 + g * KG;
+  } else {
+    pa = A.P + (uint64_t)(rr.row0 + a) * H1 + g * KG;
+  }
+  const float* pb = A.P + (uint64_t)(rr.rowB + b) * H1 + g * KG;
+  float X[NS];
+#pragma unroll
+  for (int s4 = 0; s4 < NS / 4; ++s4) {
+    float4 xa = *reinterpret_cast<const float4*>(pa + 4 * s4);
+    if (pa1) {
+      const float4 xq = *reinterpret_cast<const float4*>(pa1 + 4 * s4);
+      xa = make_float4(xa.x + xq.x, xa.y + xq.y, xa.z + xq.z, xa.w + xq.w);
+    }
+    const float4 xb = *reinterpret_cast<const float4*>(pb + 4 * s4);
+    X[4 * s4 + 0] = act_pre<ACT>(xa.x + xb.x);
+    X[4 * s4 + 1] = act_pre<ACT>(xa.y + xb.y);
+    X[4 * s4 + 2] = act_pre<ACT>(xa.z + xb.z);
+    X[4 * s4 + 3] = act_pre<ACT>(xa.w + xb.w);
+    asm volatile("" : "+v"(X[4 * s4 + 0]), "+v"(X[4 * s4 + 1]), "+v"(X[4 * s4 + 2]), "+v"(X[4 * s4 + 3])::"memory");
+  }
+  __syncthreads();  // sWo, sB2
+  // this wave's chunks: GEMM (weights in batches of B fragments, the next
+  // batch in flight), then activation and the chunk's final-layer share
+  const float* w2 = reinterpret_cast<const float*>(A.pd.w2);
+  const float* wof = sWo;
+  f32x4 hacc = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c = wave; c < NC; c += W) {
+    f32x4 acc = *reinterpret_cast<const f32x4*>(sB2 + c * 16 + g * 4);
+    const float* wc = w2 + (size_t)c * NS * 64 + lane;
+    float wb[B], wn[B];
+#pragma unroll
+    for (int e = 0; e < B; ++e) wb[e] = wc[(size_t)e * 64];
+#pragma unroll
+    for (int s0 = 0; s0 < NS; s0 += B) {
+      asm volatile("" ::: "memory");  // at most two batches of loads in flight
+      if (s0 + B < NS) {
+#pragma unroll
+        for (int e = 0; e < B; ++e) wn[e] = wc[(size_t)(s0 + B + e) * 64];
+      }
+#pragma unroll
+      for (int e = 0; e < B; ++e) acc = mma16x4(wb[e], X[s0 + e], acc);
+      if (s0 + B < NS) {
+#pragma unroll
+        for (int e = 0; e < B; ++e) wb[e] = wn[e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hacc = mma16x4(wof[(c * 4 + q) * 64 + lane], act_pre<ACT>(acc[q]), hacc);
+  }
+  sRed[wave * 64 + lane] = hacc;
+  __syncthreads();
+  if (wave != 0) return;
+  f32x4 h = sRed[lane];
+#pragma unroll
+  for (int w = 1; w < W; ++w) {
+    const f32x4 p = sRed[w * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] += p[q];
+  }
+  const uint64_t cid = v + j;
+  if (cid < A.n_ids) {
+    const float So = A.pd.scal[1];
+    float4 o4 = make_float4(fmaf(h[0], So, A.pd.bo[4 * g + 0]), fmaf(h[1], So, A.pd.bo[4 * g + 1]),
+                            fmaf(h[2], So, A.pd.bo[4 * g + 2]), fmaf(h[3], So, A.pd.bo[4 * g + 3]));
+    if (A.ids[cid] >= A.n_total) o4 = make_float4(NAN, NAN, NAN, NAN);
+    *reinterpret_cast<float4*>(A.heads_out + cid * 16 + 4 * g) = o4;
+  }
+}
+
 }  // namespace apex

@@ -239,9 +239,12 @@ __device__ inline float objective16(const float* w, const float* h) {
 // subset, threshold) and appends the passing ones to its candidate buffer. The
 // appends of a workgroup take one atomic on the query's counter (a wave prefix
 // in LDS), so a sample in which most compounds pass does not serialise on it.
+// n_src (optional): the list holds min(n, n_src->count) entries, a count known
+// only on the device.
 constexpr int kScoreThreads = 1024;
 __global__ __launch_bounds__(kScoreThreads) void k_score(const float* __restrict__ heads,
-                                                        const uint64_t* __restrict__ ids, uint32_t n,
+                                                        const uint64_t* __restrict__ ids, uint32_t n_max,
+                                                        const QState* __restrict__ n_src,
                                                         const QueryDev* __restrict__ qs, uint32_t nq,
                                                         const ReactDev* __restrict__ react, uint32_t n_react) {
   __shared__ uint32_t wave_count[kScoreThreads / 64];
@@ -251,6 +254,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const float* __restrict
   if (q >= nq) return;  // uniform per workgroup
   const QueryDev* Q = qs + q;
   if (!Q->active) return;
+  const uint32_t n = n_src ? min(n_max, n_src->count) : n_max;
   bool pass = false;
   float o = 0.0f;
   uint64_t id = 0;
@@ -300,17 +304,24 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const float* __restrict
 
 // Heads of the final answer of a low-precision search: every answer id is one of
 // the rescored pool's ids, whose FP32 heads were already computed; the row of
-// each answer id is found in LDS tiles of the pool and copied.
+// each answer id is found in LDS tiles of the pool and copied. The pool holds
+// min(pool_max, pool_src->count) entries and the answer min(want_max,
+// want_src->count), counts known only on the device.
 constexpr int kLookupThreads = 256;
 constexpr uint32_t kLookupTile = 2048;  // pool ids per workgroup
 __global__ __launch_bounds__(kLookupThreads) void k_pool_lookup(const uint64_t* __restrict__ pool_id,
                                                                const float* __restrict__ pool_heads,
-                                                               uint32_t n_pool, const uint64_t* __restrict__ want,
-                                                               uint32_t n_want, float* __restrict__ out) {
+                                                               uint32_t pool_max, const QState* __restrict__ pool_src,
+                                                               const uint64_t* __restrict__ want, uint32_t want_max,
+                                                               const QState* __restrict__ want_src,
+                                                               float* __restrict__ out) {
   // grid: x over the wanted ids, y over tiles of the pool; the one workgroup
   // whose tile holds an id writes its row
   __shared__ uint64_t tile[kLookupTile];
+  const uint32_t n_pool = min(pool_max, pool_src->count);
+  const uint32_t n_want = min(want_max, want_src->count);
   const uint32_t base = blockIdx.y * kLookupTile;
+  if (base >= n_pool) return;  // uniform per workgroup
   const uint32_t lim = n_pool - base < kLookupTile ? n_pool - base : kLookupTile;
   for (uint32_t t = threadIdx.x; t < kLookupTile; t += kLookupThreads) tile[t] = t < lim ? pool_id[base + t] : ~0ull;
   __syncthreads();
@@ -328,18 +339,253 @@ __global__ __launch_bounds__(kLookupThreads) void k_pool_lookup(const uint64_t* 
 }
 
 // ---------------------------------------------------------------------------
-// Radix select over a query's candidate buffer. After a pass over a chunk:
+// Selection over a query's candidate buffer: keep exactly the K best keys
+// (objective desc, id asc) and raise the threshold to the K-th best key.
+// After a pass over a chunk:
 //  - more entries than the buffer holds: the chunk's appends are dropped, the
 //    threshold is raised to the K-th best key among what was written (a valid
 //    lower bound of the final K-th key) and the chunk is flagged for a re-run;
-//  - more than the high-water mark (or `force`): keep exactly the K best keys
-//    (objective desc, id asc), threshold = K-th best key;
+//  - more than the high-water mark (or `force`): compaction to the K best;
 //  - otherwise: nothing but bookkeeping.
-// One workgroup per query.
+// Four launches, each deciding from the same state whether the select runs:
+//  1. k_sel_plan (one workgroup): sorts a strided sample of the keys and places
+//     kSelPivots pivots around the sample position of the K-th key;
+//  2. k_sel_count (many workgroups): exact counts of keys above each pivot;
+//  3. k_sel_compact (many workgroups): with the tightest pair of pivots that
+//     encloses the K-th key, keys above the upper one go to the output
+//     directly and keys between the two to the bracket buffer;
+//  4. k_select (one workgroup): sorts the bracket in LDS, completes the K best
+//     and updates the state. Small buffers, and brackets that do not fit, take
+//     a one-workgroup radix select instead (exact for any key distribution).
 // ---------------------------------------------------------------------------
 __device__ inline float unord_f32(uint32_t k) {
   const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
   return __uint_as_float(u);
+}
+
+// (key desc, id asc): a ranks before b
+__device__ __forceinline__ bool ranks_before(uint32_t ka, uint64_t ia, uint32_t kb, uint64_t ib) {
+  return ka > kb || (ka == kb && ia < ib);
+}
+
+struct SelPlan {
+  uint32_t n;   // valid entries
+  bool run;     // a selection happens in this call
+  bool over;    // the chunk overflowed the buffer
+};
+
+__device__ inline SelPlan sel_plan(const QueryDev& Q, int force) {
+  const QState* st = Q.st;
+  const uint32_t count = st->count;
+  SelPlan p;
+  p.over = count > Q.cap;
+  p.n = p.over ? Q.cap : count;
+  p.run = p.over || (force ? p.n > Q.K : count > Q.hwm);
+  return p;
+}
+
+constexpr uint32_t kSelPivotMin = 12288;  // smaller buffers take the radix path
+constexpr uint32_t kSelGrid = 128;        // workgroups per query of the counting passes
+constexpr uint32_t kSelPassThreads = 256;
+
+// The bracket: the lowest pivot u with fewer than K keys above it (keys above u
+// are all kept; none: u = "infinity") and the highest pivot l with at least K
+// keys at or above it (the K-th key is >= l; none: l = 0). Keys in [l, u]
+// number cnt_ge(l) - cnt_gt(u).
+struct Bracket {
+  uint32_t u, l, above, total;  // total: keys >= l
+  bool u_inf;
+  bool fits;
+};
+
+__device__ inline Bracket sel_bracket(const SelScratch* S, uint32_t n, uint32_t K) {
+  Bracket b;
+  b.u = 0xffffffffu;
+  b.u_inf = true;
+  b.above = 0;
+  for (int j = 0; j < kSelPivots; ++j)
+    if (S->cnt_gt[j] < K) {
+      b.u = S->piv[j];
+      b.u_inf = false;
+      b.above = S->cnt_gt[j];
+    }
+  b.l = 0;
+  b.total = n;
+  for (int j = kSelPivots - 1; j >= 0; --j)
+    if (S->cnt_ge[j] >= K) {
+      b.l = S->piv[j];
+      b.total = S->cnt_ge[j];
+    }
+  b.fits = b.total - b.above <= kSelBracket;
+  return b;
+}
+
+// Float4 range [b4, e4) of this workgroup's share of n entries (the n % 4
+// tail goes to workgroup 0 as single entries).
+__device__ inline void sel_share(uint32_t n, uint32_t& b4, uint32_t& e4) {
+  const uint32_t n4 = n / 4;
+  const uint32_t per = (n4 + gridDim.x - 1) / gridDim.x;
+  b4 = min(n4, blockIdx.x * per);
+  e4 = min(n4, b4 + per);
+}
+
+__global__ __launch_bounds__(kSelectThreads) void k_sel_plan(const QueryDev* __restrict__ qs, int force) {
+  const QueryDev Q = qs[blockIdx.x];
+  if (!Q.active) return;
+  const SelPlan p = sel_plan(Q, force);
+  if (!p.run) return;
+  SelScratch* S = Q.sel;
+  const uint32_t tid = threadIdx.x;
+  if (p.n < kSelPivotMin) {
+    if (tid == 0) S->mode = 1;
+    return;
+  }
+  __shared__ uint32_t samp[kSelSample];
+  for (uint32_t i = tid; i < kSelSample; i += kSelectThreads)
+    samp[i] = ord_f32(Q.cand_o[((uint64_t)i * p.n) / kSelSample]);
+  if (tid < kSelPivots) {
+    S->cnt_gt[tid] = 0;
+    S->cnt_ge[tid] = 0;
+  }
+  if (tid == 0) {
+    S->pos_sure = 0;
+    S->pos_br = 0;
+    S->mode = 0;
+  }
+  __syncthreads();
+  // bitonic sort, descending
+  for (uint32_t size = 2; size <= kSelSample; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = tid; t < kSelSample / 2; t += kSelectThreads) {
+        const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
+        const bool desc = (i & size) == 0;
+        const uint32_t a = samp[i], b = samp[j];
+        if ((a < b) == desc) {
+          samp[i] = b;
+          samp[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // pivots at sample positions r + d * 4 sd around the expected position r of
+  // the K-th key (sd: binomial spread of that position)
+  if (tid < kSelPivots) {
+    const float d[kSelPivots] = {-4.0f, -2.0f, -1.0f, -0.25f, 0.25f, 1.0f, 2.0f, 4.0f};
+    const float r = (float)Q.K * kSelSample / (float)p.n;
+    const float sd = sqrtf(fmaxf(r * (1.0f - r / kSelSample), 0.0f)) + 1.0f;
+    const float pos = fminf(fmaxf(r + d[tid] * 4.0f * sd, 0.0f), (float)(kSelSample - 1));
+    S->piv[tid] = samp[(uint32_t)pos];
+  }
+}
+
+__global__ __launch_bounds__(kSelPassThreads) void k_sel_count(const QueryDev* __restrict__ qs, int force) {
+  const QueryDev Q = qs[blockIdx.y];
+  if (!Q.active) return;
+  const SelPlan p = sel_plan(Q, force);
+  if (!p.run) return;
+  SelScratch* S = Q.sel;
+  if (S->mode) return;
+  __shared__ uint32_t part[2 * kSelPivots];
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  if (tid < 2 * kSelPivots) part[tid] = 0;
+  uint32_t pv[kSelPivots];
+#pragma unroll
+  for (int j = 0; j < kSelPivots; ++j) pv[j] = S->piv[j];
+  __syncthreads();
+  uint32_t gt[kSelPivots] = {}, ge[kSelPivots] = {};
+  auto add = [&](float o) {
+    const uint32_t kf = ord_f32(o);
+#pragma unroll
+    for (int j = 0; j < kSelPivots; ++j) {
+      gt[j] += kf > pv[j];
+      ge[j] += kf >= pv[j];
+    }
+  };
+  uint32_t b4, e4;
+  sel_share(p.n, b4, e4);
+  const float4* o4 = reinterpret_cast<const float4*>(Q.cand_o);
+  for (uint32_t i = b4 + tid; i < e4; i += kSelPassThreads) {
+    const float4 v = o4[i];
+    add(v.x);
+    add(v.y);
+    add(v.z);
+    add(v.w);
+  }
+  if (blockIdx.x == 0 && tid < p.n % 4) add(Q.cand_o[4 * (p.n / 4) + tid]);
+#pragma unroll
+  for (int j = 0; j < kSelPivots; ++j) {
+    uint32_t a = gt[j], b = ge[j];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      a += __shfl_xor(a, d);
+      b += __shfl_xor(b, d);
+    }
+    if (lane == 0) {
+      atomicAdd(&part[j], a);
+      atomicAdd(&part[kSelPivots + j], b);
+    }
+  }
+  __syncthreads();
+  if (tid < kSelPivots) {
+    atomicAdd(&S->cnt_gt[tid], part[tid]);
+    atomicAdd(&S->cnt_ge[tid], part[kSelPivots + tid]);
+  }
+}
+
+__global__ __launch_bounds__(kSelPassThreads) void k_sel_compact(const QueryDev* __restrict__ qs, int force) {
+  const QueryDev Q = qs[blockIdx.y];
+  if (!Q.active) return;
+  const SelPlan p = sel_plan(Q, force);
+  if (!p.run) return;
+  SelScratch* S = Q.sel;
+  if (S->mode) return;
+  const Bracket br = sel_bracket(S, p.n, Q.K);
+  if (!br.fits) return;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  // every lane of the wave calls this together
+  auto put = [&](float o, uint32_t i, bool ok) {
+    const uint32_t kf = ord_f32(o);
+    const bool sure = ok && !br.u_inf && kf > br.u;
+    const bool inb = ok && kf >= br.l && (br.u_inf || kf <= br.u);
+    const uint64_t ms = __ballot(sure), mb = __ballot(inb);
+    uint32_t ws = 0, wb = 0;
+    if (lane == 0) {
+      if (ms) ws = atomicAdd(&S->pos_sure, (uint32_t)__popcll(ms));
+      if (mb) wb = atomicAdd(&S->pos_br, (uint32_t)__popcll(mb));
+    }
+    ws = (uint32_t)__shfl((int)ws, 0);
+    wb = (uint32_t)__shfl((int)wb, 0);
+    if (sure) {  // fewer than K of these in all
+      const uint32_t q = ws + (uint32_t)__popcll(ms & below);
+      Q.tmp_o[q] = o;
+      Q.tmp_id[q] = Q.cand_id[i];
+    }
+    if (inb) {  // at most kSelBracket of these in all
+      const uint32_t q = wb + (uint32_t)__popcll(mb & below);
+      S->br_key[q] = kf;
+      S->br_id[q] = Q.cand_id[i];
+    }
+  };
+  uint32_t b4, e4;
+  sel_share(p.n, b4, e4);
+  const float4* o4 = reinterpret_cast<const float4*>(Q.cand_o);
+  // uniform trip count per wave, so that every lane takes part in the ballots
+  for (uint32_t i0 = b4; i0 < e4; i0 += kSelPassThreads) {
+    const uint32_t i = i0 + tid;
+    const bool ok = i < e4;
+    const float4 v = ok ? o4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    put(v.x, 4 * i, ok);
+    put(v.y, 4 * i + 1, ok);
+    put(v.z, 4 * i + 2, ok);
+    put(v.w, 4 * i + 3, ok);
+  }
+  if (blockIdx.x == 0) {
+    const uint32_t i = 4 * (p.n / 4) + tid;
+    const bool ok = tid < p.n % 4;
+    put(ok ? Q.cand_o[i] : 0.0f, i, ok);
+  }
 }
 
 // Adds one to hist[digit] for every active lane. Lanes of a wave that share a
@@ -394,29 +640,48 @@ __device__ inline void scan_objectives(const float* __restrict__ o, uint32_t n, 
   f(ok ? o[i] : 0.f, i, ok);
 }
 
-__global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __restrict__ qs, uint32_t chunk_id,
-                                                          int force) {
-  const QueryDev Q = qs[blockIdx.x];
-  if (!Q.active) return;
-  QState* st = Q.st;
-  const uint32_t tid = threadIdx.x;
+// Digit search over 256 histogram bins by the first wave. Descending: the bin
+// b with sum over bins above b < need <= the same sum including b; ascending:
+// likewise from bin 0 up. Lane l holds four consecutive bins in visit order; a
+// wave prefix sum finds the lane, the lane its bin.
+template <bool DESC>
+__device__ inline void digit_search(const uint32_t* hist, uint32_t need, uint32_t* s_digit, uint32_t* s_need,
+                                    uint32_t* s_eq) {
+  if (threadIdx.x >= 64) return;
+  const uint32_t l = threadIdx.x;
+  const uint32_t b0 = 4 * (DESC ? 63 - l : l);
+  uint32_t h[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) h[e] = hist[DESC ? b0 + 3 - e : b0 + e];
+  const uint32_t sl = h[0] + h[1] + h[2] + h[3];
+  uint32_t inc = sl;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(inc, d);
+    if (l >= (uint32_t)d) inc += v;
+  }
+  const uint32_t exc = inc - sl;
+  if (exc < need && need <= inc) {
+    uint32_t cum = exc;
+    int e = 0;
+    for (; e < 3; ++e) {
+      if (cum + h[e] >= need) break;
+      cum += h[e];
+    }
+    *s_digit = DESC ? b0 + 3 - e : b0 + e;
+    *s_need = need - cum;
+    if (s_eq) *s_eq = h[e];
+  }
+}
+
+// One-workgroup radix select: the K-th key T (8-bit digits of the order key)
+// and, when keys equal to T must be split, the id cutoff I (ids ascending);
+// then the K best go to tmp.
+__device__ inline void radix_select(const QueryDev& Q, uint32_t n, uint32_t* T_out, uint64_t* I_out) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
   __shared__ uint32_t hist[256];
   __shared__ uint32_t s_digit, s_need, s_eq, s_pos;
-  const uint32_t count = st->count;
-  const uint32_t base = st->chunk_base;
-  const bool over = count > Q.cap;
-  const uint32_t n = over ? Q.cap : count;
   const uint32_t K = Q.K;
-  const bool run = over || (force ? n > K : count > Q.hwm);
-  __syncthreads();
-  if (!run) {
-    if (tid == 0) {
-      st->appended += count - base;
-      st->chunk_base = count;
-    }
-    return;
-  }
-  // ---- K-th largest order key of the objective ----
   uint32_t prefix = 0, pmask = 0, need = K;
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (uint32_t b = tid; b < 256; b += kSelectThreads) hist[b] = 0;
@@ -426,17 +691,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
       hist_add(hist, (kf >> shift) & 255u, ok && (kf & pmask) == prefix);
     });
     __syncthreads();
-    if (tid == 0) {
-      uint32_t cum = 0;
-      int b = 255;
-      for (; b > 0; --b) {
-        if (cum + hist[b] >= need) break;
-        cum += hist[b];
-      }
-      s_digit = (uint32_t)b;
-      s_need = need - cum;
-      s_eq = hist[b];
-    }
+    digit_search<true>(hist, need, &s_digit, &s_need, &s_eq);
     __syncthreads();
     prefix |= s_digit << shift;
     pmask |= 255u << shift;
@@ -445,7 +700,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
   }
   const uint32_t T = prefix;
   const uint32_t eq = s_eq;  // entries whose key equals T
-  // ---- among ties on the objective: the `need` smallest ids ----
+  // among ties on the objective: the `need` smallest ids
   uint64_t I = ~0ull;
   if (need < eq) {
     uint64_t ip = 0, im = 0;
@@ -459,16 +714,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
         hist_add(hist, (uint32_t)(id >> shift) & 255u, tie && (id & im) == ip);
       });
       __syncthreads();
-      if (tid == 0) {
-        uint32_t cum = 0;
-        int b = 0;
-        for (; b < 255; ++b) {
-          if (cum + hist[b] >= want) break;
-          cum += hist[b];
-        }
-        s_digit = (uint32_t)b;
-        s_need = want - cum;
-      }
+      digit_search<false>(hist, want, &s_digit, &s_need, nullptr);
       __syncthreads();
       ip |= (uint64_t)s_digit << shift;
       im |= 255ull << shift;
@@ -477,22 +723,9 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
     }
     I = ip;
   }
-  const float To = unord_f32(T);
-  if (over) {
-    if (tid == 0) {
-      st->tau_o = To;
-      st->tau_id = I;
-      st->appended += count - base;
-      st->count = base;
-      st->overflow += 1;
-      Q.rerun[chunk_id] = 1u;
-    }
-    return;
-  }
-  // ---- compaction to exactly K entries (one LDS atomic per wave) ----
+  // the K best to tmp (one LDS atomic per wave)
   if (tid == 0) s_pos = 0;
   __syncthreads();
-  const uint32_t lane = tid & 63;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   scan_objectives(Q.cand_o, n, [&](float o, uint32_t i, bool ok) {
     const uint32_t kf = ord_f32(o);
@@ -504,13 +737,102 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
     if (lane == 0 && m) wbase = atomicAdd(&s_pos, (uint32_t)__popcll(m));
     wbase = (uint32_t)__shfl((int)wbase, 0);
     if (keep) {
-      const uint32_t p = wbase + (uint32_t)__popcll(m & below);
-      if (p < K) {
-        Q.tmp_o[p] = o;
-        Q.tmp_id[p] = id;
+      const uint32_t q = wbase + (uint32_t)__popcll(m & below);
+      if (q < K) {
+        Q.tmp_o[q] = o;
+        Q.tmp_id[q] = id;
       }
     }
   });
+  *T_out = T;
+  *I_out = I;
+}
+
+// Sorts the bracket in LDS (key desc, id asc) and writes its first K - above
+// entries after the `above` sure ones in tmp; returns the K-th key and id.
+__device__ inline void bracket_finish(const QueryDev& Q, const SelScratch* S, uint32_t above, uint32_t* T_out,
+                                      uint64_t* I_out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
+  uint32_t* bk = reinterpret_cast<uint32_t*>(sel_smem);
+  uint64_t* bi = reinterpret_cast<uint64_t*>(sel_smem + 4 * kSelBracket);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t m = S->pos_br;
+  uint32_t P2 = 64;
+  while (P2 < m) P2 <<= 1;
+  for (uint32_t i = tid; i < P2; i += kSelectThreads) {
+    const bool in = i < m;
+    bk[i] = in ? S->br_key[i] : 0u;  // padding ranks last
+    bi[i] = in ? S->br_id[i] : ~0ull;
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= P2; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = tid; t < P2 / 2; t += kSelectThreads) {
+        const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
+        const bool first = (i & size) == 0;
+        const uint32_t ka = bk[i], kb = bk[j];
+        const uint64_t ia = bi[i], ib = bi[j];
+        if (ranks_before(kb, ib, ka, ia) == first) {
+          bk[i] = kb;
+          bk[j] = ka;
+          bi[i] = ib;
+          bi[j] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const uint32_t take = Q.K - above;  // 1 <= take <= m
+  for (uint32_t i = tid; i < take; i += kSelectThreads) {
+    Q.tmp_o[above + i] = unord_f32(bk[i]);
+    Q.tmp_id[above + i] = bi[i];
+  }
+  *T_out = bk[take - 1];
+  *I_out = bi[take - 1];
+}
+
+__global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __restrict__ qs, uint32_t chunk_id,
+                                                          int force) {
+  const QueryDev Q = qs[blockIdx.x];
+  if (!Q.active) return;
+  QState* st = Q.st;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t count = st->count;
+  const uint32_t base = st->chunk_base;
+  const SelPlan p = sel_plan(Q, force);
+  const uint32_t K = Q.K;
+  __syncthreads();  // every thread has read the state before it changes
+  if (!p.run) {
+    if (tid == 0) {
+      st->appended += count - base;
+      st->chunk_base = count;
+    }
+    return;
+  }
+  const SelScratch* S = Q.sel;
+  uint32_t T;
+  uint64_t I;
+  bool radix = S->mode != 0;
+  uint32_t above = 0;
+  if (!radix) {
+    const Bracket br = sel_bracket(S, p.n, K);
+    radix = !br.fits;
+    above = br.above;
+  }
+  if (radix) radix_select(Q, p.n, &T, &I);
+  else bracket_finish(Q, S, above, &T, &I);
+  const float To = unord_f32(T);
+  if (p.over) {
+    if (tid == 0) {
+      st->tau_o = To;
+      st->tau_id = I;
+      st->appended += count - base;
+      st->count = base;
+      st->overflow += 1;
+      Q.rerun[chunk_id] = 1u;
+    }
+    return;
+  }
   __syncthreads();
   for (uint32_t i = tid; i < K; i += kSelectThreads) {
     Q.cand_o[i] = Q.tmp_o[i];
@@ -523,6 +845,18 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __res
     st->chunk_base = K;
     st->tau_o = To;
     st->tau_id = I;
+  }
+}
+
+// Fresh threshold state: no threshold, nothing appended.
+__global__ void k_state_reset(QState* st) {
+  if (threadIdx.x == 0) {
+    st->tau_o = -INFINITY;
+    st->tau_id = ~0ull;
+    st->count = 0;
+    st->chunk_base = 0;
+    st->overflow = 0;
+    st->appended = 0;
   }
 }
 
@@ -716,27 +1050,41 @@ hipError_t launch_bias(const float* b2, uint32_t h2, uint32_t h2k, float c, cons
   return hipGetLastError();
 }
 
-hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,
-                        const ReactDev* react, uint32_t n_react, hipStream_t s) {
+hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QState* n_src, const QueryDev* qs,
+                        uint32_t nq, const ReactDev* react, uint32_t n_react, hipStream_t s) {
   if (n == 0 || nq == 0) return hipSuccess;
   hipLaunchKernelGGL(k_score, dim3((n + kScoreThreads - 1) / kScoreThreads, nq), dim3(kScoreThreads), 0, s, heads,
-                     ids, n, qs, nq, react, n_react);
+                     ids, n, n_src, qs, nq, react, n_react);
   return hipGetLastError();
 }
 
-hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, uint32_t n_pool, const uint64_t* want,
-                              uint32_t n_want, float* out, hipStream_t s) {
-  if (n_want == 0) return hipSuccess;
-  if (n_pool == 0) return hipErrorInvalidValue;
+hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, uint32_t pool_max,
+                              const QState* pool_src, const uint64_t* want, uint32_t want_max, const QState* want_src,
+                              float* out, hipStream_t s) {
+  if (want_max == 0 || pool_max == 0) return hipSuccess;
+  if (!pool_src || !want_src) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pool_lookup,
-                     dim3((n_want + kLookupThreads - 1) / kLookupThreads, (n_pool + kLookupTile - 1) / kLookupTile),
-                     dim3(kLookupThreads), 0, s, pool_id, pool_heads, n_pool, want, n_want, out);
+                     dim3((want_max + kLookupThreads - 1) / kLookupThreads, (pool_max + kLookupTile - 1) / kLookupTile),
+                     dim3(kLookupThreads), 0, s, pool_id, pool_heads, pool_max, pool_src, want, want_max, want_src,
+                     out);
   return hipGetLastError();
 }
 
 hipError_t launch_select(const QueryDev* qs, uint32_t nq, uint32_t chunk_id, int force, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_select, dim3(nq), dim3(kSelectThreads), 0, s, qs, chunk_id, force);
+  constexpr size_t lds = 12 * kSelBracket;  // bracket keys and ids
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(k_sel_plan, dim3(nq), dim3(kSelectThreads), 0, s, qs, force);
+  hipLaunchKernelGGL(k_sel_count, dim3(kSelGrid, nq), dim3(kSelPassThreads), 0, s, qs, force);
+  hipLaunchKernelGGL(k_sel_compact, dim3(kSelGrid, nq), dim3(kSelPassThreads), 0, s, qs, force);
+  hipLaunchKernelGGL(k_select, dim3(nq), dim3(kSelectThreads), lds, s, qs, chunk_id, force);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_reset(QState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 

@@ -6,7 +6,7 @@ namespace apex {
 
 hipError_t launch_enum(int prec, int h1, int nl, int act, bool gather, const EnumArgs& a, uint32_t grid,
                        hipStream_t s);
-int enum_rows_per_block_wave(int prec);  // R: blocks of 16 compounds per wave
+uint32_t gather_per_block(int prec, int nl);  // listed compounds per workgroup of a gather launch
 hipError_t enum_prepare(int prec, int h1, int nl, int act, bool gather, uint32_t h2, int* max_wg_per_cu);
 
 hipError_t launch_hoist(const float* U, uint32_t d, uint64_t rows, const float* W1, const float* b1, uint32_t n_w,
@@ -26,12 +26,16 @@ hipError_t launch_frag_out32(const float* Wo, uint32_t H, uint32_t h2, uint32_t 
 hipError_t launch_frag_out_d(const float* Wo, uint32_t H, uint32_t h2, float mul, void* out, hipStream_t s);
 hipError_t launch_bias(const float* b2, uint32_t h2, uint32_t h2k, float c, const float* scal, const float* bo,
                        uint32_t H, float* b2_out, float* bo_out, hipStream_t s);
-hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq,
-                        const ReactDev* react, uint32_t n_react, hipStream_t s);
-hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, uint32_t n_pool, const uint64_t* want,
-                              uint32_t n_want, float* out, hipStream_t s);
+// n_src (optional): score min(n, n_src->count) entries
+hipError_t launch_score(const float* heads, const uint64_t* ids, uint32_t n, const QState* n_src, const QueryDev* qs,
+                        uint32_t nq, const ReactDev* react, uint32_t n_react, hipStream_t s);
+// pool of min(pool_max, pool_src->count) entries, answer of min(want_max, want_src->count)
+hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, uint32_t pool_max,
+                              const QState* pool_src, const uint64_t* want, uint32_t want_max, const QState* want_src,
+                              float* out, hipStream_t s);
 hipError_t launch_select(const QueryDev* qs, uint32_t nq, uint32_t chunk_id, int force, hipStream_t s);
 hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s);
+hipError_t launch_state_reset(QState* st, hipStream_t s);
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
                             hipStream_t s);
 hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t* ids, const QState* st, uint32_t K,

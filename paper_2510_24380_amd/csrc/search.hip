@@ -117,26 +117,64 @@ void query_sizes(const apex_query* q, QPlan& P) {
 
 void query_layout(uint32_t T, uint32_t n_flags, Bump& b, QPlan& p) {
   p.n_flags = n_flags;
-  p.st = b.take<QState>(1);
   p.cand_o = b.take<float>(p.cap);
   p.cand_id = b.take<uint64_t>(p.cap);
   p.tmp_o = b.take<float>(p.K);
   p.tmp_id = b.take<uint64_t>(p.K);
-  p.rerun = b.take<uint32_t>(n_flags);
   p.subset_dev = b.take<uint32_t>((T + 31) / 32);
+  p.sel = b.take<SelScratch>(1);
   if (p.lowp) {
     p.pool_heads = b.take<float>((size_t)p.K * kHeadsPad);
-    p.st2 = b.take<QState>(1);
     p.cand2_o = b.take<float>(p.cap2);
     p.cand2_id = b.take<uint64_t>(p.cap2);
     p.tmp2_o = b.take<float>(p.k);
     p.tmp2_id = b.take<uint64_t>(p.k);
   }
+}
+
+void out_layout(Bump& b, QPlan& p) {
+  const size_t off0 = b.off;
+  p.out = b.base ? b.base + off0 : nullptr;
+  p.st = b.take<QState>(1);
+  if (p.lowp) p.st2 = b.take<QState>(1);
+  p.rerun = b.take<uint32_t>(p.n_flags);
   p.fin_o = b.take<float>(p.k);
   p.fin_id = b.take<uint64_t>(p.k);
   p.fin_heads = b.take<float>((size_t)p.k * kHeadsPad);
   p.fin_reaction = b.take<uint32_t>(p.k);
   p.fin_synthon = b.take<uint32_t>((size_t)p.k * 3);
+  p.out_bytes = b.off - off0;
+}
+
+Readback::Readback(apex_engine* E, size_t bytes) : E_(E), bytes_(bytes) {
+  {
+    std::lock_guard<std::mutex> lk(E->pin_mu);
+    for (size_t i = 0; i < E->pin_free.size(); ++i)
+      if (E->pin_free[i].second >= bytes) {
+        p_ = (char*)E->pin_free[i].first;
+        bytes_ = E->pin_free[i].second;
+        E->pin_free.erase(E->pin_free.begin() + (long)i);
+        pinned_ = true;
+        return;
+      }
+  }
+  const size_t want = std::max<size_t>(bytes, 1 << 20);
+  void* p = nullptr;
+  if (hipHostMalloc(&p, want, hipHostMallocDefault) == hipSuccess) {
+    p_ = (char*)p;
+    bytes_ = want;
+    pinned_ = true;
+  } else {
+    (void)hipGetLastError();
+    host_.resize(bytes);
+    p_ = host_.data();
+  }
+}
+
+Readback::~Readback() {
+  if (!pinned_) return;
+  std::lock_guard<std::mutex> lk(E_->pin_mu);
+  E_->pin_free.emplace_back(p_, bytes_);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
@@ -192,6 +230,7 @@ QueryDev make_qdev(const apex_engine* E, const apex_query* q, const QPlan& p, bo
     d.hwm = p.cap2;
   }
   d.subset_bits = q->n_subset ? p.subset_dev : nullptr;
+  d.sel = p.sel;
   d.active = 1;
   return d;
 }
@@ -206,11 +245,7 @@ std::vector<uint32_t> subset_bits(const apex_engine* E, const apex_query* q) {
 }
 
 apex_status query_device_init(const apex_engine* E, const apex_query* q, const QPlan& P, hipStream_t s) {
-  QState init{};
-  init.tau_o = -INFINITY;
-  init.tau_id = ~0ull;
-  HIP_TRY(hipMemcpyAsync(P.st, &init, sizeof(QState), hipMemcpyHostToDevice, s));
-  if (P.lowp) HIP_TRY(hipMemcpyAsync(P.st2, &init, sizeof(QState), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_state_reset(P.st, s));  // st2: reset by finish_launch
   const std::vector<uint32_t> bits = subset_bits(E, q);
   if (!bits.empty())
     HIP_TRY(hipMemcpyAsync(P.subset_dev, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, s));
@@ -300,65 +335,62 @@ apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_
   HIP_TRY(launch_sample_ids(plan_dev, n_sel, E->react, n_comp, n_sample, 0xa5e7c0de1234ull, ids, s));
   apex_status st = engine_gather(E, prec, ids, n_sample, heads, s);
   if (st != APEX_OK) return st;
-  HIP_TRY(launch_score(heads, ids, n_sample, qd_dev, nq, E->react, E->lib->T, s));
+  HIP_TRY(launch_score(heads, ids, n_sample, nullptr, qd_dev, nq, E->react, E->lib->T, s));
   HIP_TRY(launch_select(qd_dev, nq, 0, 1, s));
   HIP_TRY(launch_tau_relax(qd_dev, nq, s));
   return APEX_OK;
 }
 
-apex_status finish_query(apex_engine* E, const apex_query* q, const QPlan& P, const QueryDev* qd_dev,
-                         const QueryDev* qx_dev, hipStream_t s, apex_result* res, const QState* st_known) {
-  (void)q;
-  QState st1{}, st2{};
-  if (st_known) {
-    st1 = *st_known;
-  } else {
-    HIP_TRY(hipMemcpyAsync(&st1, P.st, sizeof(QState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
-  const uint32_t n1 = std::min(st1.count, P.K);
-  uint32_t n_found = 0;
+apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev, const QueryDev* qx_dev,
+                          hipStream_t s) {
   if (!P.lowp) {
     HIP_TRY(launch_rank_sort(qd_dev, 0, P.K, P.fin_o, P.fin_id, s));
-    n_found = n1;
-  } else if (n1 > 0) {
-    apex_status st = engine_gather(E, APEX_PREC_FP32, P.cand_id, n1, P.pool_heads, s);
+    // rows past the answer's length are computed from stale ids and never read
+    apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, P.k, P.fin_heads, s);
     if (st != APEX_OK) return st;
-    HIP_TRY(launch_score(P.pool_heads, P.cand_id, n1, qx_dev, 1, E->react, E->lib->T, s));
+  } else {
+    // the pool is the first min(count, K) entries; the scoring ignores the rest
+    HIP_TRY(launch_state_reset(P.st2, s));  // this may be a second pass after re-runs
+    apex_status st = engine_gather(E, APEX_PREC_FP32, P.cand_id, P.K, P.pool_heads, s);
+    if (st != APEX_OK) return st;
+    HIP_TRY(launch_score(P.pool_heads, P.cand_id, P.K, P.st, qx_dev, 1, E->react, E->lib->T, s));
     HIP_TRY(launch_select(qx_dev, 1, 0, 1, s));
     HIP_TRY(launch_rank_sort(qx_dev, 0, P.k, P.fin_o, P.fin_id, s));
-    HIP_TRY(hipMemcpyAsync(&st2, P.st2, sizeof(QState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    n_found = std::min(st2.count, P.k);
-  }
-  res->n_found = n_found;
-  res->n_candidates = st1.appended;
-  if (n_found == 0) return APEX_OK;
-  std::vector<float> heads;
-  if (P.lowp) {  // the answer is part of the rescored pool
-    HIP_TRY(launch_pool_lookup(P.cand_id, P.pool_heads, n1, P.fin_id, n_found, P.fin_heads, s));
-  } else {
-    apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, n_found, P.fin_heads, s);
-    if (st != APEX_OK) return st;
+    // the answer is part of the rescored pool
+    HIP_TRY(launch_pool_lookup(P.cand_id, P.pool_heads, P.K, P.st, P.fin_id, P.k, P.st2, P.fin_heads, s));
   }
   HIP_TRY(launch_decode(E->react, E->lib->T, P.fin_id, P.lowp ? P.st2 : P.st, P.k, P.fin_reaction, P.fin_synthon,
                         s));
-  HIP_TRY(hipMemcpyAsync(res->ids, P.fin_id, sizeof(uint64_t) * n_found, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(res->objective, P.fin_o, sizeof(float) * n_found, hipMemcpyDeviceToHost, s));
-  if (res->heads) {
-    heads.resize((size_t)n_found * kHeadsPad);
-    HIP_TRY(hipMemcpyAsync(heads.data(), P.fin_heads, sizeof(float) * n_found * kHeadsPad, hipMemcpyDeviceToHost,
-                           s));
-  }
-  if (res->reaction)
-    HIP_TRY(hipMemcpyAsync(res->reaction, P.fin_reaction, sizeof(uint32_t) * n_found, hipMemcpyDeviceToHost, s));
-  if (res->synthon)
-    HIP_TRY(hipMemcpyAsync(res->synthon, P.fin_synthon, sizeof(uint32_t) * 3 * n_found, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (res->heads)
-    for (uint32_t e = 0; e < n_found; ++e)
-      std::memcpy(res->heads + (size_t)e * E->H, heads.data() + (size_t)e * kHeadsPad, sizeof(float) * E->H);
   return APEX_OK;
+}
+
+namespace {
+template <class T>
+const T* in_copy(const char* host, const char* base, const T* dev) {
+  return reinterpret_cast<const T*>(host + ((const char*)dev - base));
+}
+}  // namespace
+
+const uint32_t* out_flags(const QPlan& P, const char* host, const char* base) {
+  return in_copy(host, base, P.rerun);
+}
+
+void finish_read(const apex_engine* E, const QPlan& P, const char* host, const char* base, apex_result* res) {
+  const QState st1 = *in_copy(host, base, P.st);
+  const uint32_t n1 = std::min(st1.count, P.K);
+  const uint32_t n_found = P.lowp ? std::min(in_copy(host, base, P.st2)->count, P.k) : n1;
+  res->n_found = n_found;
+  res->n_candidates = st1.appended;
+  if (n_found == 0) return;
+  std::memcpy(res->ids, in_copy(host, base, P.fin_id), sizeof(uint64_t) * n_found);
+  std::memcpy(res->objective, in_copy(host, base, P.fin_o), sizeof(float) * n_found);
+  if (res->heads) {
+    const float* h = in_copy(host, base, P.fin_heads);
+    for (uint32_t e = 0; e < n_found; ++e)
+      std::memcpy(res->heads + (size_t)e * E->H, h + (size_t)e * kHeadsPad, sizeof(float) * E->H);
+  }
+  if (res->reaction) std::memcpy(res->reaction, in_copy(host, base, P.fin_reaction), sizeof(uint32_t) * n_found);
+  if (res->synthon) std::memcpy(res->synthon, in_copy(host, base, P.fin_synthon), sizeof(uint32_t) * 3 * n_found);
 }
 
 }  // namespace apex
@@ -399,6 +431,7 @@ void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& 
   sh.sample_ids = b.take<uint64_t>(sh.n_sample);
   sh.sample_heads = b.take<float>((size_t)sh.n_sample * kHeadsPad);
   for (uint32_t i = 0; i < n; ++i) query_layout(T, sh.n_flags, b, P[i]);
+  for (uint32_t i = 0; i < n; ++i) out_layout(b, P[i]);  // adjacent readback blocks
 }
 
 }  // namespace
@@ -478,17 +511,23 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   scored += n_comp;
   HIP_TRY(launch_select(sh.qd, nq, last_flag, 1, s));
 
-  // re-runs of chunks whose appends overflowed a candidate buffer
-  std::vector<uint32_t> flags((size_t)nq * sh.n_flags);
-  std::vector<QState> states(nq);  // read with the flags: final when no chunk needs a re-run
+  // 3-4. answers, enqueued behind the enumeration; one readback of every
+  // query's block then shows whether a chunk overflowed a candidate buffer, in
+  // which case those chunks are re-run and the answers enqueued again
+  const char* base = P[0].out;
+  const size_t span = (size_t)((P[nq - 1].out + P[nq - 1].out_bytes) - base);
+  Readback rb(E, span);
   uint32_t reruns = 0;
   for (int round = 0;; ++round) {
     for (uint32_t i = 0; i < nq; ++i) {
-      HIP_TRY(hipMemcpyAsync(flags.data() + (size_t)i * sh.n_flags, P[i].rerun, sizeof(uint32_t) * sh.n_flags,
-                             hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(&states[i], P[i].st, sizeof(QState), hipMemcpyDeviceToHost, s));
+      apex_status st = finish_launch(E, P[i], sh.qd + i, sh.qx + i, s);
+      if (st != APEX_OK) return st;
     }
+    HIP_TRY(hipMemcpyAsync(rb.data(), base, span, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    std::vector<uint32_t> flags((size_t)nq * sh.n_flags);
+    for (uint32_t i = 0; i < nq; ++i)
+      std::memcpy(flags.data() + (size_t)i * sh.n_flags, out_flags(P[i], rb.data(), base), 4 * sh.n_flags);
     bool any = false;
     for (uint32_t f : flags) any |= f != 0;
     if (!any) break;
@@ -517,11 +556,8 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
     HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_select(sh.qd, nq, last_flag, 1, s));
   }
-
-  // 3-4. answer of each query
   for (uint32_t i = 0; i < nq; ++i) {
-    apex_status st = finish_query(E, &qs[i], P[i], sh.qd + i, sh.qx + i, s, &res[i], &states[i]);
-    if (st != APEX_OK) return st;
+    finish_read(E, P[i], rb.data(), base, &res[i]);
     res[i].n_scored = scored;
     res[i].n_reruns = reruns;
   }

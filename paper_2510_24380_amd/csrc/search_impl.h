@@ -19,10 +19,15 @@ struct Bump {
   }
 };
 
-// Device buffers and sizes of one query.
+// Device buffers and sizes of one query. The threshold states, the overflow
+// flags and the answer form one contiguous readback block [out, out + out_bytes)
+// (out_layout), which the host reads in one copy once the search's device work
+// is enqueued; the blocks of a batch's queries are adjacent.
 struct QPlan {
   uint32_t k = 0, K = 0, cap = 0, hwm = 0, cap2 = 0, n_flags = 0;
   bool lowp = false;
+  char* out = nullptr;
+  size_t out_bytes = 0;
   QState* st = nullptr;
   float* cand_o = nullptr;
   uint64_t* cand_id = nullptr;
@@ -30,6 +35,7 @@ struct QPlan {
   uint64_t* tmp_id = nullptr;
   uint32_t* rerun = nullptr;      // [n_flags] per-chunk overflow flags
   uint32_t* subset_dev = nullptr; // [ceil(T/32)]
+  SelScratch* sel = nullptr;      // selection scratch (both stages)
   float* pool_heads = nullptr;
   QState* st2 = nullptr;
   float* cand2_o = nullptr;
@@ -48,8 +54,10 @@ std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint
 uint32_t tile_compounds(int prec);
 apex_status validate_query(const apex_engine* E, const apex_query* q);
 void query_sizes(const apex_query* q, QPlan& P);
-// Per-query buffers (n_flags overflow flags) from a bump allocator.
+// Per-query working buffers from a bump allocator (sets n_flags); then
+// out_layout takes the query's readback block.
 void query_layout(uint32_t n_reactions, uint32_t n_flags, Bump& b, QPlan& P);
+void out_layout(Bump& b, QPlan& P);
 QueryDev make_qdev(const apex_engine* E, const apex_query* q, const QPlan& p, bool relaxed, bool stage2);
 std::vector<uint32_t> subset_bits(const apex_engine* E, const apex_query* q);
 // Threshold state, subset bits and overflow flags of a fresh query (async).
@@ -64,12 +72,38 @@ uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev
 apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_comp,
                        uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev, uint32_t nq,
                        hipStream_t s);
-// Answer of one query whose enumeration is complete (stage 3-4; synchronises s).
-// st_known: the query's threshold state as already read back after its last
-// select (saves a synchronisation), or nullptr.
-apex_status finish_query(apex_engine* E, const apex_query* q, const QPlan& P, const QueryDev* qd_dev,
-                         const QueryDev* qx_dev, hipStream_t s, apex_result* res,
-                         const QState* st_known = nullptr);
+// Stage 3-4 device work of a query whose enumeration has been enqueued (async):
+// FP32 rescoring of a low-precision pool, the ordered answer, its heads and
+// decoding, all into the readback block. Every count it needs is read on the
+// device, so it is enqueued without a synchronisation; if the host then finds
+// an overflow flag set in the block, the chunk re-runs follow and this is
+// enqueued again.
+apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev, const QueryDev* qx_dev,
+                          hipStream_t s);
+// Overflow flags of the query in a host copy of readback blocks that starts at
+// block `base` (the first block of the copy).
+const uint32_t* out_flags(const QPlan& P, const char* host, const char* base);
+// Fills res (n_found, n_candidates and the requested arrays) from a host copy of
+// readback blocks that starts at block `base`.
+void finish_read(const apex_engine* E, const QPlan& P, const char* host, const char* base, apex_result* res);
+
+// A pinned host buffer from the engine's pool (ordinary host memory if pinning
+// fails), returned to the pool on destruction.
+class Readback {
+ public:
+  Readback(apex_engine* E, size_t bytes);
+  ~Readback();
+  Readback(const Readback&) = delete;
+  Readback& operator=(const Readback&) = delete;
+  char* data() { return p_; }
+
+ private:
+  apex_engine* E_;
+  char* p_ = nullptr;
+  size_t bytes_ = 0;
+  bool pinned_ = false;
+  std::vector<char> host_;
+};
 // Resolves the engine's pending kernel timings (after a synchronisation).
 apex_status profile_collect(apex_engine* E);
 

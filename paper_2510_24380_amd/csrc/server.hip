@@ -144,6 +144,7 @@ size_t query_bytes(const apex_server* S, const apex_query* q, QPlan* P) {
   query_sizes(q, *P);
   Bump b(nullptr);
   query_layout(S->E->lib->T, (uint32_t)S->chunks.size() + 1, b, *P);
+  out_layout(b, *P);
   return b.off;
 }
 
@@ -206,6 +207,7 @@ apex_status admit(apex_server* S, SQ* q) {
   apex_engine* E = S->E;
   Bump b(S->arena + q->off);
   query_layout(E->lib->T, (uint32_t)S->chunks.size() + 1, b, q->P);
+  out_layout(b, q->P);
   apex_status st = query_device_init(E, &q->q, q->P, S->s);
   if (st != APEX_OK) return st;
   S->qd[q->slot] = make_qdev(E, &q->q, q->P, true, false);
@@ -248,11 +250,17 @@ apex_status finalize(apex_server* S, SQ* q) {
   if (st != APEX_OK) return st;
   hipError_t e = launch_select(S->qd_dev + q->slot, 1, last_flag, 1, S->s);
   if (e != hipSuccess) return set_error(APEX_E_DEVICE, "select: %s", hipGetErrorString(e));
+  // the answer is enqueued behind the last select; one readback of the query's
+  // block then shows whether any chunk overflowed and must be re-run first
   std::vector<uint32_t> flags(S->chunks.size() + 1);
+  Readback rb(E, q->P.out_bytes);
   for (int round = 0;; ++round) {
-    e = hipMemcpyAsync(flags.data(), q->P.rerun, sizeof(uint32_t) * flags.size(), hipMemcpyDeviceToHost, S->s);
+    st = finish_launch(E, q->P, S->qd_dev + q->slot, S->qx_dev + q->slot, S->s);
+    if (st != APEX_OK) return st;
+    e = hipMemcpyAsync(rb.data(), q->P.out, q->P.out_bytes, hipMemcpyDeviceToHost, S->s);
     if (e == hipSuccess) e = hipStreamSynchronize(S->s);
     if (e != hipSuccess) return set_error(APEX_E_DEVICE, "readback: %s", hipGetErrorString(e));
+    std::memcpy(flags.data(), out_flags(q->P, rb.data(), q->P.out), sizeof(uint32_t) * flags.size());
     bool any = false;
     for (uint32_t f : flags) any |= f != 0;
     if (!any) break;
@@ -283,8 +291,7 @@ apex_status finalize(apex_server* S, SQ* q) {
   r.heads = q->heads.data();
   r.reaction = q->reaction.data();
   r.synthon = q->synthon.data();
-  st = finish_query(E, &q->q, q->P, S->qd_dev + q->slot, S->qx_dev + q->slot, S->s, &r);
-  if (st != APEX_OK) return st;
+  finish_read(E, q->P, rb.data(), q->P.out, &r);
   q->n_found = r.n_found;
   q->n_candidates = r.n_candidates;
   return APEX_OK;

@@ -197,6 +197,51 @@ def test_ties_lower_id_wins():
     assert any(o[i] == o[i + 1] for i in range(len(o) - 1))
 
 
+@pytest.fixture(scope="module")
+def dup_lib():
+    """90,000 compounds with only 200 distinct embeddings (10 distinct rows in
+    slot 0, 20 in slot 1): every objective is shared by 450 compounds."""
+    lib_h = g.make_library(53, [2], [300, 300], 64)
+    for r in range(300):
+        lib_h.tables[r] = lib_h.tables[r % 10]
+        lib_h.tables[300 + r] = lib_h.tables[300 + r % 20]
+    dec_h = g.make_decoder(53, [64, 128, 5], ACT_RELU)
+    return lib_h, dec_h, device_objects(lib_h, dec_h, precisions=("fp32",))
+
+
+def test_many_ties_large_buffers(dup_lib):
+    """Selections over tens of thousands of candidates (the sampled-pivot path)
+    split a K-th key shared by hundreds of compounds by id; the same with many
+    small chunks and a forced small buffer (overflow re-runs)."""
+    lib_h, dec_h, (lib, dec, eng) = dup_lib
+    print("case: many ties, large buffers", flush=True)
+    q = Query(w=np.array([1, 0, 0, 0, 0], np.float32), constraints=[], k=5000)
+    r = eng.search(q, precision="fp32")
+    check_fp32_exact(lib_h, dec_h, q, r, "many ties")
+    assert r.objective[-1] == r.objective[-2]
+    # the first 32,768-compound chunk overflows a 14,000-entry buffer
+    os.environ["APEX_TEST_CHUNK"] = "32768"
+    os.environ["APEX_TEST_CAP"] = "14000"
+    try:
+        r2 = eng.search(q, precision="fp32")
+    finally:
+        del os.environ["APEX_TEST_CHUNK"]
+        del os.environ["APEX_TEST_CAP"]
+    print(f"reruns={r2.n_reruns}", flush=True)
+    assert r2.n_reruns > 0
+    assert np.array_equal(r2.ids, r.ids) and np.array_equal(r2.objective, r.objective)
+
+
+def test_all_equal_objectives(dup_lib):
+    """A zero objective ties every compound: the answer is the k smallest ids."""
+    lib_h, dec_h, (lib, dec, eng) = dup_lib
+    print("case: all objectives equal", flush=True)
+    q = Query(w=np.zeros(5, np.float32), constraints=[], k=5000)
+    r = eng.search(q, precision="fp32")
+    assert np.array_equal(r.ids, np.arange(5000, dtype=np.uint64))
+    assert np.all(r.objective == 0.0)
+
+
 def test_ids_beyond_32_bits():
     """A first reaction of 4.9e9 compounds pushes the second reaction's ids past
     2^32; a subset query on the second reaction returns the exact ids."""
