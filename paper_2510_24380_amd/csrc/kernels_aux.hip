@@ -303,39 +303,30 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const float* __restrict
 }
 
 // Heads of the final answer of a low-precision search: every answer id is one of
-// the rescored pool's ids, whose FP32 heads were already computed; the row of
-// each answer id is found in LDS tiles of the pool and copied. The pool holds
-// min(pool_max, pool_src->count) entries and the answer min(want_max,
-// want_src->count), counts known only on the device.
+// the rescored pool's ids, whose FP32 heads were already computed. One wave per
+// answer id scans the pool's ids (pool ids are distinct) and copies the row.
+// The pool holds min(pool_max, pool_src->count) entries and the answer
+// min(want_max, want_src->count), counts known only on the device.
 constexpr int kLookupThreads = 256;
-constexpr uint32_t kLookupTile = 2048;  // pool ids per workgroup
 __global__ __launch_bounds__(kLookupThreads) void k_pool_lookup(const uint64_t* __restrict__ pool_id,
                                                                const float* __restrict__ pool_heads,
                                                                uint32_t pool_max, const QState* __restrict__ pool_src,
                                                                const uint64_t* __restrict__ want, uint32_t want_max,
                                                                const QState* __restrict__ want_src,
                                                                float* __restrict__ out) {
-  // grid: x over the wanted ids, y over tiles of the pool; the one workgroup
-  // whose tile holds an id writes its row
-  __shared__ uint64_t tile[kLookupTile];
   const uint32_t n_pool = min(pool_max, pool_src->count);
   const uint32_t n_want = min(want_max, want_src->count);
-  const uint32_t base = blockIdx.y * kLookupTile;
-  if (base >= n_pool) return;  // uniform per workgroup
-  const uint32_t lim = n_pool - base < kLookupTile ? n_pool - base : kLookupTile;
-  for (uint32_t t = threadIdx.x; t < kLookupTile; t += kLookupThreads) tile[t] = t < lim ? pool_id[base + t] : ~0ull;
-  __syncthreads();
-  const uint32_t i = blockIdx.x * kLookupThreads + threadIdx.x;
-  if (i >= n_want) return;
-  const uint64_t id = want[i];
-  uint32_t found = UINT32_MAX;
-  for (uint32_t t = 0; t < lim; ++t)
-    if (tile[t] == id) found = base + t;
-  if (found != UINT32_MAX) {
-    const float4* src = reinterpret_cast<const float4*>(pool_heads + (uint64_t)found * kHeadsPad);
-    float4* dst = reinterpret_cast<float4*>(out + (uint64_t)i * kHeadsPad);
-    for (int k4 = 0; k4 < kHeadsPad / 4; ++k4) dst[k4] = src[k4];
-  }
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t w = (blockIdx.x * kLookupThreads + threadIdx.x) >> 6;
+  if (w >= n_want) return;  // uniform per wave
+  const uint64_t id = want[w];
+  uint32_t pos = UINT32_MAX;
+  for (uint32_t t = lane; t < n_pool; t += 64)
+    if (pool_id[t] == id) pos = t;
+  const uint64_t hit = __ballot(pos != UINT32_MAX);
+  if (!hit) return;
+  const uint32_t src = (uint32_t)__shfl((int)pos, __ffsll((long long)hit) - 1);
+  if (lane < kHeadsPad) out[(uint64_t)w * kHeadsPad + lane] = pool_heads[(uint64_t)src * kHeadsPad + lane];
 }
 
 // ---------------------------------------------------------------------------
@@ -542,49 +533,92 @@ __global__ __launch_bounds__(kSelPassThreads) void k_sel_compact(const QueryDev*
   if (S->mode) return;
   const Bracket br = sel_bracket(S, p.n, Q.K);
   if (!br.fits) return;
-  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  constexpr uint32_t NW = kSelPassThreads / 64;
+  __shared__ uint32_t w_sure[NW], w_br[NW], s_base[2];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  // every lane of the wave calls this together
-  auto put = [&](float o, uint32_t i, bool ok) {
-    const uint32_t kf = ord_f32(o);
-    const bool sure = ok && !br.u_inf && kf > br.u;
-    const bool inb = ok && kf >= br.l && (br.u_inf || kf <= br.u);
-    const uint64_t ms = __ballot(sure), mb = __ballot(inb);
-    uint32_t ws = 0, wb = 0;
-    if (lane == 0) {
-      if (ms) ws = atomicAdd(&S->pos_sure, (uint32_t)__popcll(ms));
-      if (mb) wb = atomicAdd(&S->pos_br, (uint32_t)__popcll(mb));
-    }
-    ws = (uint32_t)__shfl((int)ws, 0);
-    wb = (uint32_t)__shfl((int)wb, 0);
-    if (sure) {  // fewer than K of these in all
-      const uint32_t q = ws + (uint32_t)__popcll(ms & below);
-      Q.tmp_o[q] = o;
-      Q.tmp_id[q] = Q.cand_id[i];
-    }
-    if (inb) {  // at most kSelBracket of these in all
-      const uint32_t q = wb + (uint32_t)__popcll(mb & below);
-      S->br_key[q] = kf;
-      S->br_id[q] = Q.cand_id[i];
-    }
-  };
   uint32_t b4, e4;
   sel_share(p.n, b4, e4);
   const float4* o4 = reinterpret_cast<const float4*>(Q.cand_o);
-  // uniform trip count per wave, so that every lane takes part in the ballots
-  for (uint32_t i0 = b4; i0 < e4; i0 += kSelPassThreads) {
-    const uint32_t i = i0 + tid;
-    const bool ok = i < e4;
-    const float4 v = ok ? o4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    put(v.x, 4 * i, ok);
-    put(v.y, 4 * i + 1, ok);
-    put(v.z, 4 * i + 2, ok);
-    put(v.w, 4 * i + 3, ok);
-  }
-  if (blockIdx.x == 0) {
-    const uint32_t i = 4 * (p.n / 4) + tid;
-    const bool ok = tid < p.n % 4;
-    put(ok ? Q.cand_o[i] : 0.0f, i, ok);
+  // one extra round in workgroup 0 for the n % 4 tail; trip count uniform per
+  // workgroup (barriers inside)
+  const uint32_t rounds = (e4 - b4 + kSelPassThreads - 1) / kSelPassThreads + (blockIdx.x == 0 ? 1 : 0);
+  for (uint32_t r = 0; r < rounds; ++r) {
+    float o[4];
+    uint32_t idx[4];
+    bool ok[4];
+    const bool tail = blockIdx.x == 0 && r + 1 == rounds;
+    if (!tail) {
+      const uint32_t i = b4 + r * kSelPassThreads + tid;
+      const bool in = i < e4;
+      const float4 v = in ? o4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        idx[c] = 4 * i + c;
+        ok[c] = in;
+      }
+    } else {
+      const uint32_t i = 4 * (p.n / 4) + tid;
+      const bool in = tid < p.n % 4;
+      o[0] = in ? Q.cand_o[i] : 0.0f;
+      idx[0] = i;
+      ok[0] = in;
+#pragma unroll
+      for (int c = 1; c < 4; ++c) {
+        o[c] = 0.0f;
+        idx[c] = 0;
+        ok[c] = false;
+      }
+    }
+    uint64_t ms[4], mb[4];
+    uint32_t ns = 0, nb = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t kf = ord_f32(o[c]);
+      const bool sure = ok[c] && !br.u_inf && kf > br.u;
+      const bool inb = ok[c] && kf >= br.l && (br.u_inf || kf <= br.u);
+      ms[c] = __ballot(sure);
+      mb[c] = __ballot(inb);
+      ns += (uint32_t)__popcll(ms[c]);
+      nb += (uint32_t)__popcll(mb[c]);
+    }
+    if (lane == 0) {
+      w_sure[wave] = ns;
+      w_br[wave] = nb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t ts = 0, tb = 0;
+      for (uint32_t w = 0; w < NW; ++w) {
+        ts += w_sure[w];
+        tb += w_br[w];
+      }
+      s_base[0] = ts ? atomicAdd(&S->pos_sure, ts) : 0u;
+      s_base[1] = tb ? atomicAdd(&S->pos_br, tb) : 0u;
+    }
+    __syncthreads();
+    uint32_t qs_ = s_base[0], qb = s_base[1];
+    for (uint32_t w = 0; w < wave; ++w) {
+      qs_ += w_sure[w];
+      qb += w_br[w];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if ((ms[c] >> lane) & 1) {  // fewer than K of these in all
+        const uint32_t q = qs_ + (uint32_t)__popcll(ms[c] & below);
+        Q.tmp_o[q] = o[c];
+        Q.tmp_id[q] = Q.cand_id[idx[c]];
+      }
+      if ((mb[c] >> lane) & 1) {  // at most kSelBracket of these in all
+        const uint32_t q = qb + (uint32_t)__popcll(mb[c] & below);
+        S->br_key[q] = ord_f32(o[c]);
+        S->br_id[q] = Q.cand_id[idx[c]];
+      }
+      qs_ += (uint32_t)__popcll(ms[c]);
+      qb += (uint32_t)__popcll(mb[c]);
+    }
+    __syncthreads();  // w_sure / w_br are rewritten by the next round
   }
 }
 
@@ -748,47 +782,85 @@ __device__ inline void radix_select(const QueryDev& Q, uint32_t n, uint32_t* T_o
   *I_out = I;
 }
 
-// Sorts the bracket in LDS (key desc, id asc) and writes its first K - above
-// entries after the `above` sure ones in tmp; returns the K-th key and id.
+// The bracket's `take` = K - above best entries, by a radix select over the
+// bracket held in LDS (8-bit digits of the key, then of the id among ties), go
+// after the `above` sure entries in tmp; returns the K-th key and id cutoff.
 __device__ inline void bracket_finish(const QueryDev& Q, const SelScratch* S, uint32_t above, uint32_t* T_out,
                                       uint64_t* I_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
   uint32_t* bk = reinterpret_cast<uint32_t*>(sel_smem);
   uint64_t* bi = reinterpret_cast<uint64_t*>(sel_smem + 4 * kSelBracket);
-  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t s_digit, s_need, s_eq, s_pos;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t m = S->pos_br;
-  uint32_t P2 = 64;
-  while (P2 < m) P2 <<= 1;
-  for (uint32_t i = tid; i < P2; i += kSelectThreads) {
-    const bool in = i < m;
-    bk[i] = in ? S->br_key[i] : 0u;  // padding ranks last
-    bi[i] = in ? S->br_id[i] : ~0ull;
+  for (uint32_t i = tid; i < m; i += kSelectThreads) {
+    bk[i] = S->br_key[i];
+    bi[i] = S->br_id[i];
   }
   __syncthreads();
-  for (uint32_t size = 2; size <= P2; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t t = tid; t < P2 / 2; t += kSelectThreads) {
-        const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
-        const bool first = (i & size) == 0;
-        const uint32_t ka = bk[i], kb = bk[j];
-        const uint64_t ia = bi[i], ib = bi[j];
-        if (ranks_before(kb, ib, ka, ia) == first) {
-          bk[i] = kb;
-          bk[j] = ka;
-          bi[i] = ib;
-          bi[j] = ia;
-        }
-      }
+  // calls f(key, index, valid) for every bracket entry, lanes of a wave in step
+  auto each = [&](auto&& f) {
+    for (uint32_t i0 = 0; i0 < m; i0 += kSelectThreads) {
+      const uint32_t i = i0 + tid;
+      const bool ok = i < m;
+      f(ok ? bk[i] : 0u, i, ok);
+    }
+  };
+  const uint32_t take = Q.K - above;  // 1 <= take <= m
+  uint32_t prefix = 0, pmask = 0, need = take;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (uint32_t b = tid; b < 256; b += kSelectThreads) hist[b] = 0;
+    __syncthreads();
+    each([&](uint32_t kf, uint32_t, bool ok) { hist_add(hist, (kf >> shift) & 255u, ok && (kf & pmask) == prefix); });
+    __syncthreads();
+    digit_search<true>(hist, need, &s_digit, &s_need, &s_eq);
+    __syncthreads();
+    prefix |= s_digit << shift;
+    pmask |= 255u << shift;
+    need = s_need;
+    __syncthreads();
+  }
+  const uint32_t T = prefix;
+  uint64_t I = ~0ull;
+  if (need < s_eq) {
+    uint64_t ip = 0, im = 0;
+    uint32_t want = need;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (uint32_t b = tid; b < 256; b += kSelectThreads) hist[b] = 0;
+      __syncthreads();
+      each([&](uint32_t kf, uint32_t i, bool ok) {
+        const bool tie = ok && kf == T;
+        const uint64_t id = tie ? bi[i] : 0ull;
+        hist_add(hist, (uint32_t)(id >> shift) & 255u, tie && (id & im) == ip);
+      });
+      __syncthreads();
+      digit_search<false>(hist, want, &s_digit, &s_need, nullptr);
+      __syncthreads();
+      ip |= (uint64_t)s_digit << shift;
+      im |= 255ull << shift;
+      want = s_need;
       __syncthreads();
     }
+    I = ip;
   }
-  const uint32_t take = Q.K - above;  // 1 <= take <= m
-  for (uint32_t i = tid; i < take; i += kSelectThreads) {
-    Q.tmp_o[above + i] = unord_f32(bk[i]);
-    Q.tmp_id[above + i] = bi[i];
-  }
-  *T_out = bk[take - 1];
-  *I_out = bi[take - 1];
+  if (tid == 0) s_pos = 0;
+  __syncthreads();
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  each([&](uint32_t kf, uint32_t i, bool ok) {
+    const bool keep = ok && (kf > T || (kf == T && bi[i] <= I));
+    const uint64_t mk = __ballot(keep);
+    uint32_t wbase = 0;
+    if (lane == 0 && mk) wbase = atomicAdd(&s_pos, (uint32_t)__popcll(mk));
+    wbase = (uint32_t)__shfl((int)wbase, 0);
+    if (keep) {
+      const uint32_t q = wbase + (uint32_t)__popcll(mk & below);
+      Q.tmp_o[above + q] = unord_f32(kf);
+      Q.tmp_id[above + q] = bi[i];
+    }
+  });
+  *T_out = T;
+  *I_out = I;
 }
 
 __global__ __launch_bounds__(kSelectThreads) void k_select(const QueryDev* __restrict__ qs, uint32_t chunk_id,
@@ -878,6 +950,48 @@ __global__ void k_tau_relax(const QueryDev* __restrict__ qs, uint32_t nq) {
   st->count = 0;
   st->chunk_base = 0;
   st->appended = 0;
+}
+
+// Sort of up to kSelBracket entries (n = min(count, K)) in one workgroup:
+// bitonic sort in LDS by (objective desc, id asc).
+__global__ __launch_bounds__(kSelectThreads) void k_sort_small(const QueryDev* __restrict__ qs, uint32_t q,
+                                                              float* __restrict__ out_o,
+                                                              uint64_t* __restrict__ out_id) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
+  uint32_t* bk = reinterpret_cast<uint32_t*>(sel_smem);
+  uint64_t* bi = reinterpret_cast<uint64_t*>(sel_smem + 4 * kSelBracket);
+  const QueryDev& Q = qs[q];
+  const uint32_t n = min(Q.st->count, Q.K);
+  const uint32_t tid = threadIdx.x;
+  uint32_t P2 = 64;
+  while (P2 < n) P2 <<= 1;
+  for (uint32_t i = tid; i < P2; i += kSelectThreads) {
+    const bool in = i < n;
+    bk[i] = in ? ord_f32(Q.cand_o[i]) : 0u;  // padding ranks last
+    bi[i] = in ? Q.cand_id[i] : ~0ull;
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= P2; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = tid; t < P2 / 2; t += kSelectThreads) {
+        const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
+        const bool first = (i & size) == 0;
+        const uint32_t ka = bk[i], kb = bk[j];
+        const uint64_t ia = bi[i], ib = bi[j];
+        if (ranks_before(kb, ib, ka, ia) == first) {
+          bk[i] = kb;
+          bk[j] = ka;
+          bi[i] = ib;
+          bi[j] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = tid; i < n; i += kSelectThreads) {
+    out_o[i] = unord_f32(bk[i]);
+    out_id[i] = bi[i];
+  }
 }
 
 // Sort n = min(count, K) entries by (objective desc, id asc): each entry's rank is
@@ -1063,10 +1177,9 @@ hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, 
                               float* out, hipStream_t s) {
   if (want_max == 0 || pool_max == 0) return hipSuccess;
   if (!pool_src || !want_src) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pool_lookup,
-                     dim3((want_max + kLookupThreads - 1) / kLookupThreads, (pool_max + kLookupTile - 1) / kLookupTile),
-                     dim3(kLookupThreads), 0, s, pool_id, pool_heads, pool_max, pool_src, want, want_max, want_src,
-                     out);
+  constexpr uint32_t waves = kLookupThreads / 64;
+  hipLaunchKernelGGL(k_pool_lookup, dim3((want_max + waves - 1) / waves), dim3(kLookupThreads), 0, s, pool_id,
+                     pool_heads, pool_max, pool_src, want, want_max, want_src, out);
   return hipGetLastError();
 }
 
@@ -1095,7 +1208,15 @@ hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s) {
 
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_rank_sort, dim3((K + 255) / 256), dim3(256), 0, s, qs, q, out_o, out_id);
+  if (K <= kSelBracket) {
+    constexpr size_t lds = 12 * kSelBracket;
+    static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_small),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSelectThreads), lds, s, qs, q, out_o, out_id);
+  } else {
+    hipLaunchKernelGGL(k_rank_sort, dim3((K + 255) / 256), dim3(256), 0, s, qs, q, out_o, out_id);
+  }
   return hipGetLastError();
 }
 
