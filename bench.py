@@ -357,6 +357,8 @@ def main():
                    "n_compounds": n, "k": q.k, "precision": args.precision},
         "recall_at_k": head["recall_at_k"],
         "exact_id_set_vs_oracle": head["exact_id_set"],
+        "candidates_appended": head["candidates"],
+        "reruns": head["reruns"],
         "roofline": roof,
         "other_precisions": others,
         "head_error_vs_fp64": {p: head_error(p) for p in (("fp32", "bf16", "fp8") if not args.quick

@@ -952,16 +952,18 @@ __global__ void k_tau_relax(const QueryDev* __restrict__ qs, uint32_t nq) {
   st->appended = 0;
 }
 
-// Sort of up to kSelBracket entries (n = min(count, K)) in one workgroup:
-// bitonic sort in LDS by (objective desc, id asc).
+// Sort of up to kSelBracket entries (n = min(count, n_max)) in one workgroup:
+// bitonic sort in LDS by (objective desc, id asc); the first min(n, n_out)
+// go out.
 __global__ __launch_bounds__(kSelectThreads) void k_sort_small(const QueryDev* __restrict__ qs, uint32_t q,
+                                                              uint32_t n_max, uint32_t n_out,
                                                               float* __restrict__ out_o,
                                                               uint64_t* __restrict__ out_id) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
   uint32_t* bk = reinterpret_cast<uint32_t*>(sel_smem);
   uint64_t* bi = reinterpret_cast<uint64_t*>(sel_smem + 4 * kSelBracket);
   const QueryDev& Q = qs[q];
-  const uint32_t n = min(Q.st->count, Q.K);
+  const uint32_t n = min(Q.st->count, n_max);
   const uint32_t tid = threadIdx.x;
   uint32_t P2 = 64;
   while (P2 < n) P2 <<= 1;
@@ -988,7 +990,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_sort_small(const QueryDev* _
       __syncthreads();
     }
   }
-  for (uint32_t i = tid; i < n; i += kSelectThreads) {
+  for (uint32_t i = tid; i < min(n, n_out); i += kSelectThreads) {
     out_o[i] = unord_f32(bk[i]);
     out_id[i] = bi[i];
   }
@@ -1206,14 +1208,22 @@ hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_sort_small(const QueryDev* qs, uint32_t q, uint32_t n_max, uint32_t n_out, float* out_o,
+                             uint64_t* out_id, hipStream_t s) {
+  if (n_max > kSelBracket) return hipErrorInvalidValue;
+  constexpr size_t lds = 12 * kSelBracket;
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_small),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSelectThreads), lds, s, qs, q, n_max, n_out, out_o, out_id);
+  return hipGetLastError();
+}
+
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
                             hipStream_t s) {
   if (K <= kSelBracket) {
-    constexpr size_t lds = 12 * kSelBracket;
-    static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_small),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSelectThreads), lds, s, qs, q, out_o, out_id);
+    hipError_t e = launch_sort_small(qs, q, K, K, out_o, out_id, s);
+    if (e != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(k_rank_sort, dim3((K + 255) / 256), dim3(256), 0, s, qs, q, out_o, out_id);
   }

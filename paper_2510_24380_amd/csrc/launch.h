@@ -38,6 +38,11 @@ hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s);
 hipError_t launch_state_reset(QState* st, hipStream_t s);
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
                             hipStream_t s);
+// Sorts min(count, n_max) <= 8192 entries of query q in one workgroup; the
+// first min(that, n_out) go out.
+hipError_t launch_sort_small(const QueryDev* qs, uint32_t q, uint32_t n_max, uint32_t n_out, float* out_o,
+                             uint64_t* out_id, hipStream_t s);
+constexpr uint32_t kSortSmallMax = 8192;
 hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t* ids, const QState* st, uint32_t K,
                          uint32_t* reaction, uint32_t* synthon, hipStream_t s);
 hipError_t launch_sample_ids(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t total, uint32_t n,

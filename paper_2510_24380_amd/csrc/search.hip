@@ -354,8 +354,13 @@ apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev
     apex_status st = engine_gather(E, APEX_PREC_FP32, P.cand_id, P.K, P.pool_heads, s);
     if (st != APEX_OK) return st;
     HIP_TRY(launch_score(P.pool_heads, P.cand_id, P.K, P.st, qx_dev, 1, E->react, E->lib->T, s));
-    HIP_TRY(launch_select(qx_dev, 1, 0, 1, s));
-    HIP_TRY(launch_rank_sort(qx_dev, 0, P.k, P.fin_o, P.fin_id, s));
+    if (P.cap2 <= kSortSmallMax) {
+      // the rescored pool fits one workgroup: sort all of it, keep the first k
+      HIP_TRY(launch_sort_small(qx_dev, 0, P.cap2, P.k, P.fin_o, P.fin_id, s));
+    } else {
+      HIP_TRY(launch_select(qx_dev, 1, 0, 1, s));
+      HIP_TRY(launch_rank_sort(qx_dev, 0, P.k, P.fin_o, P.fin_id, s));
+    }
     // the answer is part of the rescored pool
     HIP_TRY(launch_pool_lookup(P.cand_id, P.pool_heads, P.K, P.st, P.fin_id, P.k, P.st2, P.fin_heads, s));
   }
