@@ -56,7 +56,17 @@ def measured_traffic(prec, workload="c1"):
     """HBM bytes per launch of the fused kernel from the committed hardware-counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
     None when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(PROFILES, f"{fused_kernel(prec)[0]}_{prec}_{workload}_counters.md")
+    v = profile_values("counters", prec, workload)
+    try:
+        return float(v["hbm_bytes_per_launch"]) if v else None
+    except (KeyError, ValueError):
+        return None
+
+
+def profile_values(name, prec, workload="c1"):
+    """`- key: value` lines of a committed profile summary, or None when there is
+    none or the kernel sources changed since it was taken."""
+    path = os.path.join(PROFILES, f"{fused_kernel(prec)[0]}_{prec}_{workload}_{name}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -66,10 +76,28 @@ def measured_traffic(prec, workload="c1"):
             vals[k.strip("` ")] = v.strip().strip("`")
     if vals.get("kernel_sources_sha256") != kernel_sources_sha256(prec):
         return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+    return vals
+
+
+def valu_estimate(prec, flops_per_compound, compounds_per_launch, avg_launch_ms):
+    """Vector-ALU time of one launch beside its MFMA time, from the committed
+    issue-level counters: lane operations / (256 CUs x 64 lanes x 2.4 GHz), with
+    transcendentals counted once (full rate) and four times (quarter rate)."""
+    v = profile_values("sq_counters", prec)
+    if v is None:
         return None
+    lanes_per_s = 256 * 64 * 2.4e9
+    insts = float(v["valu_insts_per_compound"])
+    trans = float(v["trans_insts_per_compound"])
+    t_full = insts * 64 * compounds_per_launch / lanes_per_s
+    t_quarter = (insts + 3 * trans) * 64 * compounds_per_launch / lanes_per_s
+    t_mfma = flops_per_compound * compounds_per_launch / PEAK[prec]
+    return {"valu_insts_per_compound": insts, "trans_insts_per_compound": trans,
+            "t_valu_ms_full_rate": t_full * 1e3, "t_valu_ms_trans_quarter_rate": t_quarter * 1e3,
+            "t_mfma_ms_at_peak": t_mfma * 1e3, "t_launch_ms": avg_launch_ms,
+            "valu_bound_at_peak": t_quarter > t_mfma,
+            "measured_mfma_busy": float(v["mfma_busy"]), "measured_valu_active": float(v["valu_active"]),
+            "measured_clock_ghz": float(v["clock_ghz_under_load"])}
 
 
 def algorithmic_flops_per_compound(dims):
@@ -211,14 +239,18 @@ def main_c3(args):
     eng = apex.Engine(lib, dec, precisions=("fp32", args.precision))
     setup_s = time.perf_counter() - t0
     n = lib.num_compounds
+    log(f"engine ready ({n} compounds, {setup_s:.0f} s)")
     flops_c = algorithmic_flops_per_compound(dec_h.dims)
     for _ in range(args.warmup):
         eng.search(q, precision=args.precision)
+        log("warm-up search done")
     eng.profile(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         r = eng.search(q, precision=args.precision)
+        torch.cuda.synchronize()
+        log(f"search {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t1) / args.steps
     ms, launches, comps = eng.profile(False)
@@ -310,7 +342,8 @@ def main():
                 "frac": achieved / PEAK[prec], "traffic": measured_traffic(prec), "traffic_unit": "bytes/launch",
                 "kernel": f"apex::{fused_kernel(prec)[0]} (fused)",
                 "avg_launch_ms": avg_ms, "launches_per_step": launches / steps,
-                "compounds_per_launch": comps / max(launches, 1), "flops_per_compound": flops_c}
+                "compounds_per_launch": comps / max(launches, 1), "flops_per_compound": flops_c,
+                "valu": valu_estimate(prec, flops_c, comps / max(launches, 1), avg_ms)}
 
     sample = json.load(open(os.path.join(GOLDEN, "c1_heads_sample.json")))
     s_ids = np.array(sample["ids"], np.uint64)
