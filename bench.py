@@ -157,16 +157,17 @@ def cpu_baseline(lib_h, dec_h, q, target_s=15.0):
                       f"({tot} compounds) of the same library and query, {dt:.1f} s"}
 
 
-def serve_bench(eng, lib_h, n_queries, qps, prec="bf16", chunk_compounds=1 << 20, seed=4):
+def serve_bench(eng, counts, head_sample, n_queries, qps, size_lo, size_hi, prec="bf16", chunk_compounds=1 << 20,
+                seed=4, n_seq=None, capacity=True):
     """Continuous-batching server on a seeded Poisson stream of queries over
-    reaction subsets of the library (sizes log-uniform in [1e5, 1e7] compounds),
-    against one-query-at-a-time FP32 searches on the same arrivals."""
-    import torch
+    reaction subsets of the library (sizes log-uniform in [size_lo, size_hi]
+    compounds, thresholds at quantiles of `head_sample`, FP64 heads of seeded
+    compounds), against one-query-at-a-time FP32 searches on the same arrivals
+    (the first n_seq of them when given)."""
     import paper_2510_24380_amd as apex
     import workloads.gen as gen
-    H = np.array(json.load(open(os.path.join(GOLDEN, "c1_heads_sample.json")))["heads"])
-    counts = lib_h.reaction_counts()
-    stream = gen.serving_stream(seed, n_queries, qps, counts, 1e5, 1e7, lambda h, qq: np.quantile(H[:, h], qq))
+    stream = gen.serving_stream(seed, n_queries, qps, counts, size_lo, size_hi,
+                                lambda h, qq: np.quantile(head_sample[:, h], qq))
     sizes = [sum(counts[r] for r in q.reactions) for _, q in stream]
 
     def pct(v, p):
@@ -176,28 +177,41 @@ def serve_bench(eng, lib_h, n_queries, qps, prec="bf16", chunk_compounds=1 << 20
     srv = apex.Server(eng, pool_bytes=4 << 30, max_active=16, chunk_compounds=chunk_compounds)
     t0 = time.perf_counter()
     tickets = []
-    for t, q in stream:
+    for i, (t, q) in enumerate(stream):
         dt = t0 + t - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
         tickets.append(srv.submit(q, precision=prec))
-    served = [srv.poll(tk, timeout_ms=600000) for tk in tickets]
+        if (i + 1) % 100 == 0:
+            log(f"serving: {i + 1}/{len(stream)} submitted")
+    served = []
+    for i, tk in enumerate(tickets):
+        served.append(srv.poll(tk, timeout_ms=600000))
+        if (i + 1) % 20 == 0:
+            log(f"serving: {i + 1}/{len(tickets)} completed")
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    out = {"queries": n_queries, "qps": qps, "precision": prec, "chunk_compounds": chunk_compounds,
+           "library_sizes": [min(sizes), float(np.median(sizes)), max(sizes)],
+           "served": {"p50_latency_ms": st["p50_latency_ms"], "p99_latency_ms": st["p99_latency_ms"],
+                      "max_latency_ms": st["max_latency_ms"], "wall_s": wall,
+                      "device_compounds_per_s": st["compounds_per_s"]}}
     # 2. served, all submitted at once (capacity)
-    srv = apex.Server(eng, pool_bytes=4 << 30, max_active=16, chunk_compounds=chunk_compounds)
-    t1 = time.perf_counter()
-    tk2 = [srv.submit(q, precision=prec) for _, q in stream]
-    for tk in tk2:
-        srv.poll(tk, timeout_ms=600000)
-    cap_s = time.perf_counter() - t1
-    srv.close()
+    if capacity:
+        srv = apex.Server(eng, pool_bytes=4 << 30, max_active=16, chunk_compounds=chunk_compounds)
+        t1 = time.perf_counter()
+        tk2 = [srv.submit(q, precision=prec) for _, q in stream]
+        for tk in tk2:
+            srv.poll(tk, timeout_ms=600000)
+        out["served"]["saturated_query_compounds_per_s"] = sum(sizes) / (time.perf_counter() - t1)
+        srv.close()
     # 3. sequential FP32 on the same arrivals
+    seq_stream = stream if n_seq is None else stream[:n_seq]
     lat, seq = [], []
     t2 = time.perf_counter()
     busy = 0.0
-    for t, q in stream:
+    for t, q in seq_stream:
         dt = t2 + t - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
@@ -205,38 +219,65 @@ def serve_bench(eng, lib_h, n_queries, qps, prec="bf16", chunk_compounds=1 << 20
         seq.append(eng.search(q, precision="fp32"))
         busy += time.perf_counter() - a
         lat.append((time.perf_counter() - t2 - t) * 1e3)
+        if len(seq) % 10 == 0:
+            log(f"sequential FP32: {len(seq)}/{len(seq_stream)} done")
     recalls = [len(set(a.ids.tolist()) & set(b.ids.tolist())) / max(1, len(b.ids)) for a, b in zip(served, seq)]
-    return {
-        "queries": n_queries, "qps": qps, "precision": prec, "chunk_compounds": chunk_compounds,
-        "library_sizes": [min(sizes), float(np.median(sizes)), max(sizes)],
-        "served": {"p50_latency_ms": st["p50_latency_ms"], "p99_latency_ms": st["p99_latency_ms"],
-                   "max_latency_ms": st["max_latency_ms"], "wall_s": wall,
-                   "device_compounds_per_s": st["compounds_per_s"],
-                   "saturated_query_compounds_per_s": sum(sizes) / cap_s},
-        "sequential_fp32": {"p50_latency_ms": pct(lat, 50), "p99_latency_ms": pct(lat, 99),
-                            "max_latency_ms": max(lat), "query_compounds_per_s": sum(sizes) / busy},
-        "recall_vs_sequential_fp32": {"mean": float(np.mean(recalls)), "min": float(np.min(recalls))},
-    }
+    out["sequential_fp32"] = {"queries": len(seq_stream), "p50_latency_ms": pct(lat, 50),
+                              "p99_latency_ms": pct(lat, 99), "max_latency_ms": max(lat),
+                              "query_compounds_per_s": sum(sizes[:len(seq_stream)]) / busy}
+    out["recall_vs_sequential_fp32"] = {"mean": float(np.mean(recalls)), "min": float(np.min(recalls))}
+    return out
 
 
-def main_c3(args):
-    """The streamed 2.9e10-compound library: one step is one search over all of it."""
+def build_c3(precisions):
+    """The streamed 2.9e10-compound library and its engine (tables generated on the host)."""
     import torch
     import paper_2510_24380_amd as apex
     import workloads.gen as gen
-    from workloads.gen import Constraint, Query
-    t0 = time.perf_counter()
     lib_h, dec_h = gen.config_c3()
-    spec = json.load(open(os.path.join(GOLDEN, "c3_query.json")))["query"]
-    cons = [Constraint(c["head"], -math.inf if c["lo"] is None else c["lo"],
-                       math.inf if c["hi"] is None else c["hi"]) for c in spec["constraints"]]
-    q = Query(w=np.array(spec["w"], np.float32), constraints=cons, k=spec["k"])
+    counts = lib_h.reaction_counts()
     tables = torch.from_numpy(lib_h.tables).cuda()
     del lib_h.tables
     lib = apex.Library(lib_h.n_slots, lib_h.slot_sizes, tables)
     dec = apex.Decoder(dec_h.dims, "silu", [torch.from_numpy(w).cuda() for w in dec_h.W],
                        [torch.from_numpy(b).cuda() for b in dec_h.b])
-    eng = apex.Engine(lib, dec, precisions=("fp32", args.precision))
+    return lib_h, dec_h, counts, lib, apex.Engine(lib, dec, precisions=precisions)
+
+
+def main_c4(args):
+    """Serving at the large scale: a Poisson stream (5 queries/s) of queries over
+    reaction subsets of the 2.9e10-compound library, 1e6 to 1e9 compounds each."""
+    t0 = time.perf_counter()
+    lib_h, dec_h, counts, lib, eng = build_c3(("fp32", args.precision))
+    log(f"engine ready ({lib.num_compounds} compounds, {time.perf_counter() - t0:.0f} s)")
+    H = np.array(json.load(open(os.path.join(GOLDEN, "c3_heads_sample.json")))["heads"])
+    sv = serve_bench(eng, counts, H, args.serve_queries, args.serve_qps, 1e6, 1e9, prec=args.precision,
+                     chunk_compounds=1 << 26, seed=5, n_seq=args.seq_queries, capacity=False)
+    out = {
+        "metric": "served query compounds/s and latency (continuous batching) vs sequential FP32",
+        "value": sv["served"]["device_compounds_per_s"], "unit": "compounds/s", "n_gpus": 1,
+        "steps": args.serve_queries, "warmup": 0, "ms_per_step": sv["served"]["wall_s"] * 1e3 / args.serve_queries,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic (seeded N(0,1) synthon embeddings, Xavier-uniform decoder)",
+        "config": {"workload": f"serving: {args.serve_queries} queries, Poisson {args.serve_qps}/s, reaction "
+                               "subsets of the 2.9e10-compound synthetic CSL with 1e6-1e9 compounds each, "
+                               "random objectives over 15 heads, 2-6 bounds, k in {100, 1000, 10000}",
+                   "precision": args.precision},
+        "p99_latency_ms": sv["served"]["p99_latency_ms"],
+        "serving": sv,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main_c3(args):
+    """The streamed 2.9e10-compound library: one step is one search over all of it."""
+    from workloads.gen import Constraint, Query
+    t0 = time.perf_counter()
+    lib_h, dec_h, counts, lib, eng = build_c3(("fp32", args.precision))
+    spec = json.load(open(os.path.join(GOLDEN, "c3_query.json")))["query"]
+    cons = [Constraint(c["head"], -math.inf if c["lo"] is None else c["lo"],
+                       math.inf if c["hi"] is None else c["hi"]) for c in spec["constraints"]]
+    q = Query(w=np.array(spec["w"], np.float32), constraints=cons, k=spec["k"])
     setup_s = time.perf_counter() - t0
     n = lib.num_compounds
     log(f"engine ready ({n} compounds, {setup_s:.0f} s)")
@@ -283,12 +324,16 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--quick", action="store_true", help="headline precision only (profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3"],
-                    help="c1: 1.04e7-compound library (default); c3: 2.9e10-compound streamed library")
-    ap.add_argument("--serve-queries", type=int, default=80, help="serving stream length (0: skip)")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
+                    help="c1: 1.04e7-compound library (default); c3: 2.9e10-compound streamed library; "
+                         "c4: serving a query stream over subsets of the c3 library")
+    ap.add_argument("--serve-queries", type=int, default=None,
+                    help="serving stream length (0: skip; default 80, c4: 2000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for hardware byte counters)")
-    ap.add_argument("--serve-qps", type=float, default=100.0)
+    ap.add_argument("--serve-qps", type=float, default=None, help="arrival rate (default 100/s, c4: 5/s)")
+    ap.add_argument("--seq-queries", type=int, default=None,
+                    help="arrivals timed one at a time in FP32 for comparison (default all, c4: 20)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the search runs on a single MI355X (a multi-GPU run would split "
@@ -305,6 +350,15 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "c3":
         return main_c3(args)
+    c4 = args.workload == "c4"
+    if args.serve_queries is None:
+        args.serve_queries = 2000 if c4 else 80
+    if args.serve_qps is None:
+        args.serve_qps = 5.0 if c4 else 100.0
+    if args.seq_queries is None and c4:
+        args.seq_queries = 20
+    if c4:
+        return main_c4(args)
     lib_h, dec_h = gen.config_c1()
     q = load_query()
     tables = torch.from_numpy(lib_h.tables).to(dev)
@@ -400,7 +454,9 @@ def main():
     if "fp32" in others and args.precision != "fp32":
         out["speedup_vs_fp32"] = head["compounds_per_s"] / others["fp32"]["compounds_per_s"]
     if args.serve_queries and not args.quick:
-        out["serving"] = serve_bench(eng, lib_h, args.serve_queries, args.serve_qps)
+        H = np.array(json.load(open(os.path.join(GOLDEN, "c1_heads_sample.json")))["heads"])
+        out["serving"] = serve_bench(eng, lib_h.reaction_counts(), H, args.serve_queries, args.serve_qps, 1e5, 1e7,
+                                     n_seq=args.seq_queries)
         log("serving stream done")
         out["p99_latency_ms"] = out["serving"]["served"]["p99_latency_ms"]
     if not args.no_cpu_baseline and not args.quick:

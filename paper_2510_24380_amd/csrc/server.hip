@@ -1,13 +1,17 @@
 // Serving loop: continuous batching of queries over one engine.
 //
-// A host thread owns the device work. Submitted queries wait in FIFO order until
-// their workspace fits in the caller's memory pool and an active slot is free.
+// A host thread owns the device work. Submitted queries wait until their
+// workspace fits in the caller's memory pool and an active slot is free; the
+// smallest waiting query (compounds searched) is admitted first, except on every
+// fourth admission, which takes the oldest.
 // The library is cut into reaction-aligned chunks; every pass evaluates one chunk
 // once for all active queries (of one precision) that still need it, so the
 // combine and the decoder run once per compound for the whole group, and the
 // objective, bounds and selection run per query (the fused kernel's query loop).
 // A query joins at the next pass after admission and completes after it has
-// seen every chunk holding its reactions, wrapping around the chunk cycle; then
+// seen every chunk holding its reactions, wrapping around the chunk cycle (the
+// chunk of each pass is chosen for the active query with the fewest chunks
+// left, or on every fourth pass for the oldest one); then
 // its overflowed chunks are re-run, its pool rescored and its answer decoded and
 // copied to the host. Per-compound arithmetic does not depend on which queries
 // share a pass, so a query's result is the same alone and in any mix.
@@ -61,9 +65,13 @@ struct SQ {
   uint32_t n_reruns = 0;
 };
 
+// Reactions [r0, r1); a reaction larger than a chunk is split into chunks of
+// consecutive tiles [tile0, tile1) of that one reaction (tiles are 8 x 16
+// compounds in every precision), so that no pass runs much longer than a chunk.
 struct Chunk {
-  uint32_t r0, r1;  // reactions [r0, r1)
+  uint32_t r0, r1;
   uint64_t compounds;
+  uint64_t tile0 = 0, tile1 = UINT64_MAX;
 };
 
 // First-fit allocator over [0, size) with 256-byte granularity.
@@ -131,6 +139,7 @@ struct apex_server {
   std::vector<Chunk> chunks;
   uint32_t cursor[3] = {0, 0, 0};
   int next_prec = 0;
+  uint64_t passes = 0, admissions = 0;
   // statistics
   uint64_t submitted = 0, completed = 0, cancelled = 0, failed = 0;
   std::vector<double> latencies_ms;
@@ -190,9 +199,12 @@ apex_status run_pass(apex_server* S, int prec, uint32_t c, const std::vector<SQ*
   if (st != APEX_OK) return st;
   hipError_t e = hipMemcpyAsync(S->plan_dev, plan.data(), sizeof(SelDev) * plan.size(), hipMemcpyHostToDevice, S->s);
   if (e != hipSuccess) return set_error(APEX_E_DEVICE, "upload: %s", hipGetErrorString(e));
+  const Chunk& ch = S->chunks[c];
+  const uint64_t v0 = std::min(ch.tile0, n_tiles), v1 = std::min(ch.tile1, n_tiles);
+  if (v0 > 0 || v1 < n_tiles) n_comp = plan_compounds(S->E, prec, plan, v0, v1);
   const double t0 = now_s();
-  st = enum_pass(S->E, prec, S->plan_dev, (uint32_t)plan.size(), 0, n_tiles, S->qd_dev, (uint32_t)S->qd.size(),
-                 n_comp, S->s);
+  st = enum_pass(S->E, prec, S->plan_dev, (uint32_t)plan.size(), v0, v1, S->qd_dev, (uint32_t)S->qd.size(), n_comp,
+                 S->s);
   if (st != APEX_OK) return st;
   e = launch_select(S->qd_dev, (uint32_t)S->qd.size(), c, 0, S->s);
   if (e == hipSuccess) e = hipStreamSynchronize(S->s);
@@ -218,16 +230,10 @@ apex_status admit(apex_server* S, SQ* q) {
   // compounds searched and chunks needed
   q->need.assign(S->chunks.size(), 0);
   q->remaining = 0;
-  q->n_comp = 0;
   for (size_t c = 0; c < S->chunks.size(); ++c) {
     if (!chunk_wanted(S->chunks[c], q)) continue;
     q->need[c] = 1;
     q->remaining++;
-  }
-  if (q->subset.empty()) {
-    q->n_comp = E->lib->total;
-  } else {
-    for (uint32_t t : q->subset) q->n_comp += E->lib->id_off[t + 1] - E->lib->id_off[t];
   }
   // warm start: a sample of the whole library, scored with the query's subset
   const int prec = (int)q->q.precision;
@@ -321,15 +327,24 @@ void worker_loop(apex_server* S) {
             release_slot(S, sp.get());
             S->cv_done.notify_all();
           }
-        while (!S->pending.empty()) {
-          auto q = S->pending.front();
-          if (q->cancel) {
-            S->pending.pop_front();
-            q->state = Q_CANCELLED;
+        for (auto it = S->pending.begin(); it != S->pending.end();) {
+          if ((*it)->cancel) {
+            (*it)->state = Q_CANCELLED;
             S->cancelled++;
             S->cv_done.notify_all();
-            continue;
+            it = S->pending.erase(it);
+          } else {
+            ++it;
           }
+        }
+        while (!S->pending.empty()) {
+          // the smallest waiting query first (compounds searched), except on
+          // every fourth admission, which takes the oldest
+          size_t pick = 0;
+          if (S->admissions % 4 != 3)
+            for (size_t i = 1; i < S->pending.size(); ++i)
+              if (S->pending[i]->n_comp < S->pending[pick]->n_comp) pick = i;
+          auto q = S->pending[pick];
           int slot = -1;
           for (size_t i = 0; i < S->slots.size(); ++i)
             if (!S->slots[i]) {
@@ -339,7 +354,8 @@ void worker_loop(apex_server* S) {
           if (slot < 0) break;
           size_t off = 0;
           if (!S->pool.alloc(q->bytes, &off)) break;
-          S->pending.pop_front();
+          S->pending.erase(S->pending.begin() + (long)pick);
+          S->admissions++;
           q->off = off;
           q->slot = slot;
           q->state = Q_ACTIVE;
@@ -405,15 +421,25 @@ void worker_loop(apex_server* S) {
     }
     if (prec < 0) continue;
     S->next_prec = (prec + 1) % 3;
+    // The pass takes the next chunk (from the cursor on) that a lead query
+    // needs, and every active query of this precision that needs that chunk
+    // joins it. The lead is the query with the fewest chunks left (short
+    // queries are not held behind long ones), except on every fourth pass,
+    // where it is the oldest query (long ones keep progressing under load).
+    SQ* lead = nullptr;
+    const bool oldest = (S->passes++ % 4) == 3;
+    for (SQ* q : act[prec]) {
+      const bool better = !lead || (oldest ? q->t_submit < lead->t_submit
+                                           : (q->remaining < lead->remaining ||
+                                              (q->remaining == lead->remaining && q->t_submit < lead->t_submit)));
+      if (better) lead = q;
+    }
     const uint32_t nch = (uint32_t)S->chunks.size();
     uint32_t c = S->cursor[prec];
+    for (uint32_t step = 0; step < nch && !lead->need[c]; ++step) c = (c + 1) % nch;
     std::vector<SQ*> part;
-    for (uint32_t step = 0; step < nch; ++step, c = (c + 1) % nch) {
-      part.clear();
-      for (SQ* q : act[prec])
-        if (q->need[c]) part.push_back(q);
-      if (!part.empty()) break;
-    }
+    for (SQ* q : act[prec])
+      if (q->need[c]) part.push_back(q);
     if (part.empty()) continue;
     apex_status st = run_pass(S, prec, c, part);
     if (st != APEX_OK) {
@@ -457,19 +483,34 @@ extern "C" apex_status apex_server_create(apex_engine* eng, const apex_server_co
   S->E = eng;
   S->cfg = *cfg;
   S->s = (hipStream_t)cfg->stream;
-  // reaction-aligned chunks of about chunk_compounds
+  // chunks of about chunk_compounds: runs of whole reactions, and tile ranges of
+  // reactions larger than that
   const uint64_t target = cfg->chunk_compounds ? cfg->chunk_compounds : (1ull << 26);
   const apex_library* L = eng->lib;
   uint32_t r0 = 0;
   uint64_t acc = 0;
   for (uint32_t t = 0; t < L->T; ++t) {
-    acc += L->id_off[t + 1] - L->id_off[t];
+    const uint64_t n_t = L->id_off[t + 1] - L->id_off[t];
+    if (n_t > target) {
+      if (acc > 0) S->chunks.push_back({r0, t, acc});
+      const ReactDev& rd = eng->react_host[t];
+      const uint64_t tiles = (uint64_t)((rd.nA + tile_ta(0) - 1) / tile_ta(0)) * ((rd.nB + tile_tb(0) - 1) / tile_tb(0));
+      const uint64_t pieces = (n_t + target - 1) / target;
+      const uint64_t per = (tiles + pieces - 1) / pieces;
+      for (uint64_t v = 0; v < tiles; v += per)
+        S->chunks.push_back({t, t + 1, n_t * (std::min(tiles, v + per) - v) / tiles, v, std::min(tiles, v + per)});
+      r0 = t + 1;
+      acc = 0;
+      continue;
+    }
+    acc += n_t;
     if (acc >= target || t + 1 == L->T) {
       S->chunks.push_back({r0, t + 1, acc});
       r0 = t + 1;
       acc = 0;
     }
   }
+  if (acc > 0) S->chunks.push_back({r0, L->T, acc});
   S->n_sample = 1u << 16;
   Bump b(cfg->pool);
   S->qd_dev = b.take<QueryDev>(cfg->max_active);
@@ -514,6 +555,11 @@ extern "C" apex_status apex_server_submit(apex_server* srv, const apex_query* q,
   sq->q.constraints = sq->cons.data();
   sq->q.subset = sq->subset.data();
   sq->bytes = query_bytes(srv, &sq->q, &sq->P);
+  if (sq->subset.empty()) {
+    sq->n_comp = srv->E->lib->total;
+  } else {
+    for (uint32_t t : sq->subset) sq->n_comp += srv->E->lib->id_off[t + 1] - srv->E->lib->id_off[t];
+  }
   const size_t header = (size_t)(srv->arena - (char*)srv->cfg.pool);
   if (sq->bytes > srv->cfg.pool_bytes - header)
     return set_error(APEX_E_NOMEM, "query needs %zu bytes, more than the pool holds", sq->bytes);
