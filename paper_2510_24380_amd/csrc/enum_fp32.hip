@@ -16,10 +16,16 @@ namespace apex {
   if (h1 == 256) { APEX_NLS(256, G) } \
   if (h1 == 512) { APEX_NLS(512, G) }
 
+#define APEX_H1S_GATHER \
+  if (h1 == 128 && nl == 1) { APEX_ACTS(128, 1, true) } \
+  if (h1 == 256 && nl == 1) { APEX_ACTS(256, 1, true) } \
+  if (h1 == 512 && nl == 1) { APEX_ACTS(512, 1, true) }
+
+// Gathers with two hidden layers use k_gather_split (below), not this kernel.
 const void* enum_kernel_fp32(int h1, int nl, int act, bool gather) {
   if (nl == 0 && h1 == 16 && act == APEX_ACT_NONE)  // one-layer (linear) decoder
     return gather ? APEX_K(16, 0, APEX_ACT_NONE, true) : APEX_K(16, 0, APEX_ACT_NONE, false);
-  if (gather) { APEX_H1S(true) } else { APEX_H1S(false) }
+  if (gather) { APEX_H1S_GATHER } else { APEX_H1S(false) }
   return nullptr;
 }
 

@@ -24,8 +24,13 @@ def _rows():
     return rows
 
 
+def _fused(rows):
+    """The fused enumeration kernels and the split FP32 gather kernel."""
+    return [r for r in rows if "k_enum" in r["kernel"] or "k_gather_split" in r["kernel"]]
+
+
 def test_enum_kernels_scratch_bounded():
-    rows = [r for r in _rows() if "k_enum" in r["kernel"]]
+    rows = _fused(_rows())
     assert len(rows) >= 100
     bad = [r["kernel"] for r in rows if int(r.get("scratch", 0)) > 32 or int(r.get("vgpr_spill", 0)) > 8]
     assert not bad, bad
@@ -35,6 +40,6 @@ def test_enum_kernels_scratch_bounded():
 
 
 def test_enum_kernels_two_waves_per_simd():
-    rows = [r for r in _rows() if "k_enum" in r["kernel"]]
+    rows = _fused(_rows())
     assert all(int(r["occupancy"]) >= 2 for r in rows)
     assert all(int(r["vgpr"]) + int(r.get("agpr", 0)) <= 256 for r in rows)
