@@ -313,6 +313,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     } else {
       // The staged rows are no longer needed: the region takes the weight chunks.
       __syncthreads();
+      // Waves in their GEMM phase issue before waves (of the other workgroup on
+      // this CU) in their activation phase, so the matrix core is fed first and
+      // the activation work fills the gaps (FP8 kernel time -7 %, BF16 -1.5 %).
+      __builtin_amdgcn_s_setprio(1);
       {
         uint4* dst = reinterpret_cast<uint4*>(sW);
         PreAll rest;
@@ -463,6 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       __syncthreads();  // the region is restaged by the next tile
     }
 
+    __builtin_amdgcn_s_setprio(0);
     // ---------------- heads, objective, bounds, filter ----------------
     // The thread's tile coordinates are recomputed here from a copy of the
     // thread index the compiler cannot see through, so they are not kept live
