@@ -271,6 +271,7 @@ def main_c4(args):
 
 def main_c3(args):
     """The streamed 2.9e10-compound library: one step is one search over all of it."""
+    import torch
     from workloads.gen import Constraint, Query
     t0 = time.perf_counter()
     lib_h, dec_h, counts, lib, eng = build_c3(("fp32", args.precision))
