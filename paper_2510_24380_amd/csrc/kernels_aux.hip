@@ -1090,6 +1090,41 @@ __global__ void k_sample_ids(const SelDev* __restrict__ sel, uint32_t n_sel, con
   ids[i] = react[sel[a].t].id_off + (x - sel[a].compound_start);
 }
 
+// Sample for the threshold warm start: n compounds in groups of 32, group g
+// taking two first-slot rows (a random even pair of a tile's eight) against the
+// tile's 16 last-slot rows of one tile drawn from the g-th of equal parts of the
+// selection's tile range. Tiles of different groups differ, so no compound is
+// drawn twice (a repeated compound could push the sample's K-th key above the
+// true K-th best). A group's compounds share rows, which the gather then reads
+// once from the caches instead of once per compound. Positions outside the
+// reaction get an id past the library's end (their heads come out NaN and
+// they are not scored).
+__global__ void k_sample_tiles(const SelDev* __restrict__ sel, uint32_t n_sel, const ReactDev* __restrict__ react,
+                               uint64_t n_tiles, uint32_t n, uint64_t seed, uint64_t* __restrict__ ids) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t groups = (n + 31) / 32, g = i / 32, m = i % 32;
+  const uint64_t lo = (uint64_t)(((unsigned __int128)n_tiles * g) / groups);
+  const uint64_t hi = (uint64_t)(((unsigned __int128)n_tiles * (g + 1)) / groups);
+  uint64_t z = seed + (uint64_t)(g + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const uint64_t v = lo + (hi > lo ? z % (hi - lo) : 0);
+  uint32_t a = 0, b = n_sel;
+  while (b - a > 1) {
+    const uint32_t mid = (a + b) >> 1;
+    if (sel[mid].tile_start <= v) a = mid; else b = mid;
+  }
+  const SelDev S = sel[a];
+  const ReactDev R = react[S.t];
+  const uint64_t lt = v - S.tile_start;
+  const uint32_t ta = (uint32_t)(lt / S.tiles_b), tb = (uint32_t)(lt % S.tiles_b);
+  const uint32_t r0 = 2 * (uint32_t)((z >> 40) % 4);  // rows r0, r0 + 1 of the tile's eight
+  const uint32_t ra = ta * 8 + r0 + m / 16, rb = tb * kTileB + m % 16;
+  ids[i] = (ra < R.nA && rb < R.nB) ? R.id_off + (uint64_t)ra * R.nB + rb : ~0ull;
+}
+
 // Largest |low-precision head - FP32 head| per head.
 __global__ void k_head_err(const float* __restrict__ h_lp, const float* __restrict__ h_32, uint32_t n,
                            float* __restrict__ out) {
@@ -1239,6 +1274,13 @@ hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t
 hipError_t launch_sample_ids(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t total, uint32_t n,
                              uint64_t seed, uint64_t* ids, hipStream_t s) {
   hipLaunchKernelGGL(k_sample_ids, dim3((n + 255) / 256), dim3(256), 0, s, sel, n_sel, react, total, n, seed, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_tiles(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t n_tiles, uint32_t n,
+                               uint64_t seed, uint64_t* ids, hipStream_t s) {
+  if (tile_ta(0) != 8) return hipErrorInvalidValue;  // two of a tile's eight first-slot rows
+  hipLaunchKernelGGL(k_sample_tiles, dim3((n + 255) / 256), dim3(256), 0, s, sel, n_sel, react, n_tiles, n, seed, ids);
   return hipGetLastError();
 }
 

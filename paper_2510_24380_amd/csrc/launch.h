@@ -45,6 +45,9 @@ hipError_t launch_sort_small(const QueryDev* qs, uint32_t q, uint32_t n_max, uin
 constexpr uint32_t kSortSmallMax = 8192;
 hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t* ids, const QState* st, uint32_t K,
                          uint32_t* reaction, uint32_t* synthon, hipStream_t s);
+// Warm-start sample: groups of 32 compounds (2 x 16 of one tile) from disjoint tile strata.
+hipError_t launch_sample_tiles(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t n_tiles, uint32_t n,
+                               uint64_t seed, uint64_t* ids, hipStream_t s);
 hipError_t launch_sample_ids(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t total, uint32_t n,
                              uint64_t seed, uint64_t* ids, hipStream_t s);
 hipError_t launch_head_err(const float* h_lp, const float* h_32, uint32_t n, float* out, hipStream_t s);

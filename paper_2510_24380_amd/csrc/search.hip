@@ -329,10 +329,10 @@ apex_status profile_collect(apex_engine* E) {
   return APEX_OK;
 }
 
-apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_comp,
+apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_tiles,
                        uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev, uint32_t nq,
                        hipStream_t s) {
-  HIP_TRY(launch_sample_ids(plan_dev, n_sel, E->react, n_comp, n_sample, 0xa5e7c0de1234ull, ids, s));
+  HIP_TRY(launch_sample_tiles(plan_dev, n_sel, E->react, n_tiles, n_sample, 0xa5e7c0de1234ull, ids, s));
   apex_status st = engine_gather(E, prec, ids, n_sample, heads, s);
   if (st != APEX_OK) return st;
   HIP_TRY(launch_score(heads, ids, n_sample, nullptr, qd_dev, nq, E->react, E->lib->T, s));
@@ -497,7 +497,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   uint64_t scored = 0;
   // 1. threshold warm start from a stratified sample of the searched reactions
   if (n_comp >= 8ull * sh.n_sample) {
-    apex_status st = warm_start(E, prec, sh.plan, (uint32_t)plan.size(), n_comp, sh.n_sample, sh.sample_ids,
+    apex_status st = warm_start(E, prec, sh.plan, (uint32_t)plan.size(), n_tiles, sh.n_sample, sh.sample_ids,
                                 sh.sample_heads, sh.qd, nq, s);
     if (st != APEX_OK) return st;
     scored += sh.n_sample;

@@ -68,8 +68,9 @@ apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t
                       const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, hipStream_t s);
 // Compounds of a host tile plan inside tiles [v0, v1).
 uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev>& plan, uint64_t v0, uint64_t v1);
-// Threshold warm start from a sample of compounds for the listed queries (async).
-apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_comp,
+// Threshold warm start from a sample of compounds of a tile plan (n_tiles tiles)
+// for the listed queries (async).
+apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_tiles,
                        uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev, uint32_t nq,
                        hipStream_t s);
 // Stage 3-4 device work of a query whose enumeration has been enqueued (async):

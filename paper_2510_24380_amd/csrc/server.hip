@@ -240,7 +240,7 @@ apex_status admit(apex_server* S, SQ* q) {
   if (E->lib->total >= 8ull * S->n_sample && q->n_comp >= 8ull * S->n_sample) {
     st = upload_active(S, {q->slot});
     if (st != APEX_OK) return st;
-    st = warm_start(E, prec, E->prec[prec].plan, E->lib->T, E->prec[prec].full_compounds, S->n_sample, S->sample_ids,
+    st = warm_start(E, prec, E->prec[prec].plan, E->lib->T, E->prec[prec].full_tiles, S->n_sample, S->sample_ids,
                     S->sample_heads, S->qd_dev, (uint32_t)S->qd.size(), S->s);
     if (st != APEX_OK) return st;
     q->n_scored += S->n_sample;
