@@ -952,47 +952,51 @@ __global__ void k_tau_relax(const QueryDev* __restrict__ qs, uint32_t nq) {
   st->appended = 0;
 }
 
-// Sort of up to kSelBracket entries (n = min(count, n_max)) in one workgroup:
-// bitonic sort in LDS by (objective desc, id asc); the first min(n, n_out)
-// go out.
-__global__ __launch_bounds__(kSelectThreads) void k_sort_small(const QueryDev* __restrict__ qs, uint32_t q,
-                                                              uint32_t n_max, uint32_t n_out,
-                                                              float* __restrict__ out_o,
-                                                              uint64_t* __restrict__ out_id) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
-  uint32_t* bk = reinterpret_cast<uint32_t*>(sel_smem);
-  uint64_t* bi = reinterpret_cast<uint64_t*>(sel_smem + 4 * kSelBracket);
+// Sort of up to kSelBracket entries (n = min(count, n_max)) by (objective desc,
+// id asc), keeping the first min(n, n_out): each entry's rank is the number of
+// entries ranked before it (keys are distinct), counted over a 2D grid - block
+// x of entries against block y of entries staged in LDS, the block's count added
+// to the entry's rank - then every entry with rank < n_out is written to its
+// place. No barrier separates the comparisons, unlike a sorting network.
+constexpr uint32_t kRankBlock = 256;
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(kRankBlock) void k_rank_count(const QueryDev* __restrict__ qs, uint32_t q,
+                                                           uint32_t n_max, uint32_t* __restrict__ rank) {
   const QueryDev& Q = qs[q];
   const uint32_t n = min(Q.st->count, n_max);
-  const uint32_t tid = threadIdx.x;
-  uint32_t P2 = 64;
-  while (P2 < n) P2 <<= 1;
-  for (uint32_t i = tid; i < P2; i += kSelectThreads) {
-    const bool in = i < n;
-    bk[i] = in ? ord_f32(Q.cand_o[i]) : 0u;  // padding ranks last
-    bi[i] = in ? Q.cand_id[i] : ~0ull;
-  }
+  const uint32_t i0 = blockIdx.x * kRankBlock, j0 = blockIdx.y * kRankBlock;
+  if (i0 >= n || j0 >= n) return;  // uniform per workgroup
+  __shared__ uint32_t sk[kRankBlock];
+  __shared__ uint64_t si[kRankBlock];
+  const uint32_t t = threadIdx.x, m = min(kRankBlock, n - j0);
+  sk[t] = t < m ? ord_f32(Q.cand_o[j0 + t]) : 0u;
+  si[t] = t < m ? Q.cand_id[j0 + t] : ~0ull;
   __syncthreads();
-  for (uint32_t size = 2; size <= P2; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t t = tid; t < P2 / 2; t += kSelectThreads) {
-        const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
-        const bool first = (i & size) == 0;
-        const uint32_t ka = bk[i], kb = bk[j];
-        const uint64_t ia = bi[i], ib = bi[j];
-        if (ranks_before(kb, ib, ka, ia) == first) {
-          bk[i] = kb;
-          bk[j] = ka;
-          bi[i] = ib;
-          bi[j] = ia;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (uint32_t i = tid; i < min(n, n_out); i += kSelectThreads) {
-    out_o[i] = unord_f32(bk[i]);
-    out_id[i] = bi[i];
+  const uint32_t i = i0 + t;
+  if (i >= n) return;
+  const uint32_t ki = ord_f32(Q.cand_o[i]);
+  const uint64_t ii = Q.cand_id[i];
+  uint32_t c = 0;
+  for (uint32_t k = 0; k < m; ++k) c += ranks_before(sk[k], si[k], ki, ii) ? 1u : 0u;
+  if (c) atomicAdd(rank + i, c);
+}
+
+__global__ __launch_bounds__(kRankBlock) void k_rank_scatter(const QueryDev* __restrict__ qs, uint32_t q,
+                                                             uint32_t n_max, uint32_t n_out,
+                                                             const uint32_t* __restrict__ rank,
+                                                             float* __restrict__ out_o, uint64_t* __restrict__ out_id) {
+  const QueryDev& Q = qs[q];
+  const uint32_t n = min(Q.st->count, n_max);
+  const uint32_t i = blockIdx.x * kRankBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t r = rank[i];
+  if (r < n_out) {
+    out_o[r] = Q.cand_o[i];
+    out_id[r] = Q.cand_id[i];
   }
 }
 
@@ -1244,20 +1248,20 @@ hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s) {
 }
 
 hipError_t launch_sort_small(const QueryDev* qs, uint32_t q, uint32_t n_max, uint32_t n_out, float* out_o,
-                             uint64_t* out_id, hipStream_t s) {
+                             uint64_t* out_id, uint32_t* rank, hipStream_t s) {
   if (n_max > kSelBracket) return hipErrorInvalidValue;
-  constexpr size_t lds = 12 * kSelBracket;
-  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_small),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSelectThreads), lds, s, qs, q, n_max, n_out, out_o, out_id);
+  if (n_max == 0) return hipSuccess;
+  const uint32_t nb = (n_max + kRankBlock - 1) / kRankBlock;
+  hipLaunchKernelGGL(k_zero_u32, dim3(nb), dim3(kRankBlock), 0, s, rank, n_max);
+  hipLaunchKernelGGL(k_rank_count, dim3(nb, nb), dim3(kRankBlock), 0, s, qs, q, n_max, rank);
+  hipLaunchKernelGGL(k_rank_scatter, dim3(nb), dim3(kRankBlock), 0, s, qs, q, n_max, n_out, rank, out_o, out_id);
   return hipGetLastError();
 }
 
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
-                            hipStream_t s) {
+                            uint32_t* rank, hipStream_t s) {
   if (K <= kSelBracket) {
-    hipError_t e = launch_sort_small(qs, q, K, K, out_o, out_id, s);
+    hipError_t e = launch_sort_small(qs, q, K, K, out_o, out_id, rank, s);
     if (e != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(k_rank_sort, dim3((K + 255) / 256), dim3(256), 0, s, qs, q, out_o, out_id);

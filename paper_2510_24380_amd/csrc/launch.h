@@ -36,12 +36,14 @@ hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, 
 hipError_t launch_select(const QueryDev* qs, uint32_t nq, uint32_t chunk_id, int force, hipStream_t s);
 hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s);
 hipError_t launch_state_reset(QState* st, hipStream_t s);
+// Sorts min(count, K) entries of query q by (objective desc, id asc) into out.
+// rank: device scratch of at least min(K, 8192) uint32 (ranks of small sorts).
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
-                            hipStream_t s);
-// Sorts min(count, n_max) <= 8192 entries of query q in one workgroup; the
-// first min(that, n_out) go out.
+                            uint32_t* rank, hipStream_t s);
+// Sorts min(count, n_max) <= 8192 entries of query q; the first min(that, n_out)
+// go out. rank: device scratch of n_max uint32.
 hipError_t launch_sort_small(const QueryDev* qs, uint32_t q, uint32_t n_max, uint32_t n_out, float* out_o,
-                             uint64_t* out_id, hipStream_t s);
+                             uint64_t* out_id, uint32_t* rank, hipStream_t s);
 constexpr uint32_t kSortSmallMax = 8192;
 hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t* ids, const QState* st, uint32_t K,
                          uint32_t* reaction, uint32_t* synthon, hipStream_t s);

@@ -341,10 +341,16 @@ apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_
   return APEX_OK;
 }
 
+// The selection scratch's bracket keys (free once the selections are done)
+// hold the ranks of the answer sort.
+static uint32_t* rank_scratch(const QPlan& P) {
+  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(P.sel) + offsetof(SelScratch, br_key));
+}
+
 apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev, const QueryDev* qx_dev,
                           hipStream_t s) {
   if (!P.lowp) {
-    HIP_TRY(launch_rank_sort(qd_dev, 0, P.K, P.fin_o, P.fin_id, s));
+    HIP_TRY(launch_rank_sort(qd_dev, 0, P.K, P.fin_o, P.fin_id, rank_scratch(P), s));
     // rows past the answer's length are computed from stale ids and never read
     apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, P.k, P.fin_heads, s);
     if (st != APEX_OK) return st;
@@ -356,10 +362,10 @@ apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev
     HIP_TRY(launch_score(P.pool_heads, P.cand_id, P.K, P.st, qx_dev, 1, E->react, E->lib->T, s));
     if (P.cap2 <= kSortSmallMax) {
       // the rescored pool fits one workgroup: sort all of it, keep the first k
-      HIP_TRY(launch_sort_small(qx_dev, 0, P.cap2, P.k, P.fin_o, P.fin_id, s));
+      HIP_TRY(launch_sort_small(qx_dev, 0, P.cap2, P.k, P.fin_o, P.fin_id, rank_scratch(P), s));
     } else {
       HIP_TRY(launch_select(qx_dev, 1, 0, 1, s));
-      HIP_TRY(launch_rank_sort(qx_dev, 0, P.k, P.fin_o, P.fin_id, s));
+      HIP_TRY(launch_rank_sort(qx_dev, 0, P.k, P.fin_o, P.fin_id, rank_scratch(P), s));
     }
     // the answer is part of the rescored pool
     HIP_TRY(launch_pool_lookup(P.cand_id, P.pool_heads, P.K, P.st, P.fin_id, P.k, P.st2, P.fin_heads, s));
