@@ -79,13 +79,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int ROW = H1 + kRowPad;
   constexpr int CHUNK = 32 * H1 * M::EB;  // bytes of one 32-neuron GEMM weight chunk
   constexpr int NPRE = CHUNK / 16 / T;    // 16-byte pieces of a chunk per thread
-  constexpr int PP = NPRE > 4 ? 2 : NPRE;  // pieces per prefetch part (registers held during the GEMM)
-  constexpr int NPART = NPRE / PP;
-  constexpr int SPP = NS / NPART;          // k-steps per prefetch part
   constexpr int ROWS_BYTES = GATHER ? 0 : (TA + TB) * ROW * 4;
   constexpr int REGION = ROWS_BYTES > (NL == 2 ? 2 * CHUNK : 0) ? ROWS_BYTES : (NL == 2 ? 2 * CHUNK : 0);
   static_assert(NS * E == KH, "layout");
-  static_assert(CHUNK % (16 * T) == 0 && NPRE % PP == 0 && NS % NPART == 0, "chunk split");
+  static_assert(CHUNK % (16 * T) == 0, "chunk split");
   static_assert(NL >= 1, "the linear decoder runs in the FP32 kernel");
 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -147,18 +144,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
     return make_uint4(v[0], v[1], v[2], v[3]);
   };
-  // prefetched weights are SSA vectors (an array would stay in scratch)
-  typedef uint32_t PreV __attribute__((ext_vector_type(4 * PP)));
-  typedef uint32_t PreAll __attribute__((ext_vector_type(4 * NPRE)));
-  auto pre_put = [](auto& p, int q, uint4 w) {
-    p[4 * q] = w.x; p[4 * q + 1] = w.y; p[4 * q + 2] = w.z; p[4 * q + 3] = w.w;
+  // GEMM weight chunk c -> LDS buffer buf, by loads that write LDS directly (no
+  // registers held, no LDS stores issued): the q-th 1 KB block of wave w is
+  // bytes q T 16 + 1024 w of the chunk, placed at the same offset of the buffer,
+  // 16 bytes per lane. They are waited for right before the barrier that
+  // publishes the buffer, a whole chunk later.
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);  // wave-uniform (scalar) offsets
+  auto load_chunk = [&](int c, int buf) {
+#pragma unroll
+    for (int q = 0; q < NPRE; ++q) {
+      const uint32_t off = (uint32_t)(q * T * 16 + wave_u * 1024);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          w2r, (__attribute__((address_space(3))) void*)(sW + buf * CHUNK + off), 16, 16u * (uint32_t)lane,
+          (uint32_t)(c * CHUNK) + off, 0, 0);
+    }
   };
-  auto pre_get = [](const auto& p, int q) { return make_uint4(p[4 * q], p[4 * q + 1], p[4 * q + 2], p[4 * q + 3]); };
-  // piece q of part p of a chunk: 16 bytes per thread (index into the chunk in
-  // 16-byte units, and the global load of it from chunk c)
-  auto piece = [&](int, int p, int q) { return (uint32_t)((p * PP + q) * T + tid); };
-  auto wload = [&](int c, int p, int q) {
-    return ldb16(w2r, 16u * (uint32_t)tid, (uint32_t)(c * CHUNK + (p * PP + q) * T * 16));
+  auto publish = [&]() {  // the chunk loads of this thread done, then all threads
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
   };
 
   uint32_t si = 0;
@@ -173,13 +176,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 
   for (; v < vend; v += (GATHER ? vend : 1)) {
-    PreV pre;
-    // first part of GEMM weight chunk 0: loads issued now, stored after the
-    // activation phase (the other parts are loaded there)
-    if (NL == 2) {
-#pragma unroll
-      for (int q = 0; q < PP; ++q) pre_put(pre, q, wload(0, 0, q));
-    }
     // ---------------- locate the tile and stage its rows ----------------
     uint32_t a0 = 0, b0 = 0;
     if (!GATHER) {
@@ -317,17 +313,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       // this CU) in their activation phase, so the matrix core is fed first and
       // the activation work fills the gaps (FP8 kernel time -7 %, BF16 -1.5 %).
       __builtin_amdgcn_s_setprio(1);
-      {
-        uint4* dst = reinterpret_cast<uint4*>(sW);
-        PreAll rest;
-#pragma unroll
-        for (int q = PP; q < NPRE; ++q) pre_put(rest, q, wload(0, 0, q));
-#pragma unroll
-        for (int q = 0; q < PP; ++q) dst[piece(0, 0, q)] = pre_get(pre, q);
-#pragma unroll
-        for (int q = PP; q < NPRE; ++q) dst[piece(0, 0, q)] = pre_get(rest, q);
-      }
-      __syncthreads();
+      load_chunk(0, 0);
+      publish();
 
       // Static plan of the previous chunk's activation work over the k-steps
       // of a GEMM: activation v runs its four operations (exp2, add, rcp, mul)
@@ -350,19 +337,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         return t + 1 < NS ? t + 1 : NS - 1;
       };
 
-      // One chunk of 32 neurons: prefetch the next chunk in NPART parts through
-      // registers, run the GEMM steps into `acc`, and (fin) interleave the
-      // activation and final layer of the previous chunk (`old`, chunk c_old)
-      // with them. pf and fin are literals at every call. Each step ends in a
-      // scheduling barrier, so the interleave is the one written here: the
-      // weight read two steps ahead, the MFMA, then this step's share of the
-      // activation work.
+      // One chunk of 32 neurons: start the loads of the next chunk (pf) into
+      // the other buffer (last read in the chunk before this one, which every
+      // wave has finished), run the GEMM steps into `acc`, and (fin)
+      // interleave the activation and final layer of the previous chunk
+      // (`old`, chunk c_old) with them. pf and fin are literals at every call.
+      // Each step ends in a scheduling barrier, so the interleave is the one
+      // written here: the weight read two steps ahead, the MFMA, then this
+      // step's share of the activation work.
       auto gemm = [&](int c, f32x16& acc, bool pf, const f32x16& old, int c_old, bool fin) {
-        uint4* dst = reinterpret_cast<uint4*>(sW + ((c + 1) & 1) * CHUNK);
-        if (pf) {
-#pragma unroll
-          for (int q = 0; q < PP; ++q) pre_put(pre, q, wload(c + 1, 0, q));
-        }
+        if (pf) load_chunk(c + 1, (c + 1) & 1);
         bf16x8 wo[2];
         if (fin) {
 #pragma unroll
@@ -388,13 +372,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int s = 0; s < NS; ++s) {
           if (s + 2 < NS) ring[(s + 2) % 3] = load_frag<Frag>(wc + (size_t)((s + 2) * 64 + lane) * E * M::EB);
           acc = M::mma(ring[s % 3], X[s], acc);
-          if (pf && s % SPP == SPP - 1 && s / SPP < NPART - 1) {  // part s / SPP out, the next one in
-            const int pp = s / SPP;
-#pragma unroll
-            for (int q = 0; q < PP; ++q) dst[piece(0, pp, q)] = pre_get(pre, q);
-#pragma unroll
-            for (int q = 0; q < PP; ++q) pre_put(pre, q, wload(c + 1, pp + 1, q));
-          }
           if (fin) {
             // the operations of act_pre, one at a time (same arithmetic)
 #pragma unroll
@@ -443,24 +420,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           hacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wo, xb, hacc, 0, 0, 0);
         }
       };
-      auto publish = [&](int c, bool pf) {  // last prefetched part of chunk c + 1 -> its LDS buffer
-        if (pf) {
-          uint4* dst = reinterpret_cast<uint4*>(sW + ((c + 1) & 1) * CHUNK);
-#pragma unroll
-          for (int q = 0; q < PP; ++q) dst[piece(0, NPART - 1, q)] = pre_get(pre, q);
-        }
-        __syncthreads();
-      };
       // NC is even (the host pads the width to a multiple of 64 neurons)
       f32x16 accA, accB;
       gemm(0, accA, true, accB, 0, false);
-      publish(0, true);
+      publish();
       int c = 1;
       for (; c + 2 < NC; c += 2) {  // chunks c and c + 1 both have a successor
         gemm(c, accB, true, accA, c - 1, true);
-        publish(c, true);
+        publish();
         gemm(c + 1, accA, true, accB, c, true);
-        publish(c + 1, true);
+        publish();
       }
       gemm(c, accB, false, accA, c - 1, true);  // c == NC - 1
       finish(c, accB);
