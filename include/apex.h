@@ -49,7 +49,7 @@ typedef enum {
   APEX_E_INVALID = -1,     /* bad argument, shape or state */
   APEX_E_NOMEM = -2,       /* a caller workspace or memory budget is too small */
   APEX_E_DEVICE = -3,      /* a HIP call failed; the text names the hipError_t */
-  APEX_E_UNSUPPORTED = -4, /* valid request outside what this build implements */
+  APEX_E_UNSUPPORTED = -4, /* valid request outside what this library implements */
   APEX_E_PENDING = -5,     /* server: the query has not finished yet */
   APEX_E_CANCELLED = -6    /* server: the query was cancelled */
 } apex_status;
@@ -58,7 +58,7 @@ enum { APEX_ACT_NONE = 0, APEX_ACT_RELU = 1, APEX_ACT_SILU = 2 };
 enum { APEX_PREC_FP32 = 0, APEX_PREC_BF16 = 1, APEX_PREC_FP8 = 2 };
 #define APEX_PREC_MASK(p) (1u << (p))
 
-/* Limits of this build. */
+/* Limits of this library. */
 #define APEX_MAX_HEADS 16        /* decoder output width H */
 #define APEX_MAX_CONSTRAINTS 16  /* bounds per query */
 #define APEX_MAX_FUSED_QUERIES 32
