@@ -242,6 +242,31 @@ def test_all_equal_objectives(dup_lib):
     assert np.all(r.objective == 0.0)
 
 
+@pytest.fixture(scope="module")
+def wide():
+    """39,600 compounds (two- and three-slot reactions) for answers longer than
+    the one-workgroup sort holds."""
+    lib_h = g.make_library(59, [2, 2, 3], [150, 120, 90, 200, 20, 15, 12], 64)
+    dec_h = g.make_decoder(59, [64, 128, 128, 5], ACT_SILU)
+    return lib_h, dec_h, device_objects(lib_h, dec_h, precisions=("fp32", "bf16"))
+
+
+def test_answers_longer_than_one_workgroup_sort(wide):
+    """k = 9000 (> 8192): the FP32 answer is ordered by the multi-workgroup rank
+    sort, and the BF16 pool (36,000 entries) is selected before that sort."""
+    lib_h, dec_h, (lib, dec, eng) = wide
+    sample = oracle.heads(lib_h, dec_h, np.arange(0, lib_h.n_compounds, 7, dtype=np.uint64))
+    lo = float(np.float32(np.quantile(sample[:, 1], 0.3)))
+    q = Query(w=np.array([1, 0, -0.5, 0, 0], np.float32), constraints=[Constraint(1, lo, math.inf)], k=9000)
+    print("case: k=9000 fp32", flush=True)
+    r = eng.search(q, precision="fp32")
+    ref = check_fp32_exact(lib_h, dec_h, q, r, "k=9000 fp32")
+    assert ref.n_feasible > 9000
+    print("case: k=9000 bf16", flush=True)
+    r = eng.search(q, precision="bf16")
+    check_lowp(lib_h, dec_h, q, r, "k=9000 bf16")
+
+
 def test_ids_beyond_32_bits():
     """A first reaction of 4.9e9 compounds pushes the second reaction's ids past
     2^32; a subset query on the second reaction returns the exact ids."""
