@@ -50,6 +50,21 @@ constexpr int kTileA32 = 8;  // A-rows per tile (2 per wave)
 // untyped loads use only the range and base).
 constexpr int kBufferWord3 = 0x00020000;
 
+// Epilogue parameters of one query, copied to LDS once per tile launch: the
+// threshold and the bounds do not change during a launch (the selections that
+// move the threshold run between launches), so each tile reads them from LDS
+// instead of through the query's pointers in global memory.
+struct QLds {
+  float w[kHeadsPad];
+  float lo[kHeadsPad];
+  float hi[kHeadsPad];
+  float tau_o;
+  uint32_t active;
+  uint64_t tau_id;
+  const uint32_t* subset_bits;
+};
+constexpr int kQLdsBytes = APEX_MAX_FUSED_QUERIES * (int)sizeof(QLds);
+
 // Row of accumulator v of lane half h in a 32x32 D tile.
 __host__ __device__ constexpr int d32_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
@@ -64,7 +79,7 @@ __host__ __device__ constexpr int enum32_lds_bytes(int prec, int h1, int nl, int
   int region = rows > chunk ? rows : chunk;
   int wo = nl == 1 ? 32 * h1 * eb : 0;
   int b2 = nl == 2 ? h2 * 4 : 0;
-  return region + wo + b2 + kHeadsPad * 4;  // + final bias
+  return region + wo + b2 + kHeadsPad * 4 + (gather ? 0 : kQLdsBytes);  // + final bias, query parameters
 }
 
 template <int PREC, int H1, int NL, int ACT, bool GATHER>
@@ -94,6 +109,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // final bias, read from LDS in the epilogue (a global pointer to it would be
   // hoisted out of the tile loop and held in registers)
   float* sBo = reinterpret_cast<float*>(smem + REGION + (NL == 1 ? 32 * H1 * M::EB : 0)) + (NL == 2 ? A.H2 : 0);
+  QLds* sQ = reinterpret_cast<QLds*>(sBo + kHeadsPad);  // tile mode: one entry per query
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, j = lane & 31;
   const uint32_t H2 = NL == 2 ? A.H2 : 0;
@@ -125,6 +141,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (NL == 2)
       for (int i = tid; i < (int)H2; i += T) sB2[i] = A.pd.b2[i];
     if (tid < kHeadsPad) sBo[tid] = A.pd.bo[tid];
+    if (!GATHER) {
+      // one wave per query: lanes 0..47 copy w, lo, hi; lanes 48..51 the rest.
+      // An inactive slot (a server slot without a query) may have no state:
+      // its threshold is not read.
+      for (uint32_t qi = wave; qi < A.n_queries; qi += W) {
+        const QueryDev* Q = A.queries + qi;
+        QLds* L = sQ + qi;
+        if (lane < 3 * kHeadsPad) {
+          const float* src = lane < kHeadsPad ? Q->w : lane < 2 * kHeadsPad ? Q->lo : Q->hi;
+          float* dst = lane < kHeadsPad ? L->w : lane < 2 * kHeadsPad ? L->lo : L->hi;
+          dst[lane % kHeadsPad] = src[lane % kHeadsPad];
+        } else if (lane == 48) {
+          L->tau_o = Q->active ? Q->st->tau_o : 0.0f;
+        } else if (lane == 49) {
+          L->active = Q->active;
+        } else if (lane == 50) {
+          L->tau_id = Q->active ? Q->st->tau_id : 0ull;
+        } else if (lane == 51) {
+          L->subset_bits = Q->subset_bits;
+        }
+      }
+    }
     if (NL == 1) {
       const uint4* src = reinterpret_cast<const uint4*>(A.pd.wo);
       uint4* dst = reinterpret_cast<uint4*>(sWo);
@@ -469,20 +507,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     } else {
       for (uint32_t qi = 0; qi < A.n_queries; ++qi) {
-        const QueryDev* Q = A.queries + qi;
-        if (!Q->active) continue;
-        if (Q->subset_bits && !((Q->subset_bits[S.t >> 5] >> (S.t & 31)) & 1u)) continue;
-        const float tau_o = Q->st->tau_o;
-        const uint64_t tau_id = Q->st->tau_id;
+        const QLds* L = sQ + qi;
+        if (!L->active) continue;
+        if (L->subset_bits && !((L->subset_bits[S.t >> 5] >> (S.t & 31)) & 1u)) continue;
+        const QueryDev* Q = A.queries + qi;  // appends only
+        const float tau_o = L->tau_o;
+        const uint64_t tau_id = L->tau_id;
         // objective in the order of the other kernels: groups of four heads,
         // (g0 + g1) + (g2 + g3); this lane half holds groups h and 2 + h
-        float pA = obj_partial(Q->w + 4 * h, hd);
-        float pB = obj_partial(Q->w + 8 + 4 * h, hd + 4);
+        float pA = obj_partial(L->w + 4 * h, hd);
+        float pB = obj_partial(L->w + 8 + 4 * h, hd + 4);
         int ok = 1;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int hh = d32_row(q, h);
-          ok &= (hd[q] >= Q->lo[hh]) & (hd[q] <= Q->hi[hh]);
+          ok &= (hd[q] >= L->lo[hh]) & (hd[q] <= L->hi[hh]);
         }
         const float oA = __shfl_xor(pA, 32), oB = __shfl_xor(pB, 32);
         ok &= __shfl_xor(ok, 32);

@@ -276,6 +276,8 @@ uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev
 
 apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t v0, uint64_t v1,
                       const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, hipStream_t s) {
+  // the tile kernels keep every fused query's parameters in LDS
+  if (nq == 0 || nq > APEX_MAX_FUSED_QUERIES) return set_error(APEX_E_INVALID, "internal: %u fused queries", nq);
   const PrecState& PS = E->prec[prec];
   EnumArgs a{};
   a.P = E->P;
