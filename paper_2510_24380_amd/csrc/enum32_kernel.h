@@ -50,21 +50,6 @@ constexpr int kTileA32 = 8;  // A-rows per tile (2 per wave)
 // untyped loads use only the range and base).
 constexpr int kBufferWord3 = 0x00020000;
 
-// Epilogue parameters of one query, copied to LDS once per tile launch: the
-// threshold and the bounds do not change during a launch (the selections that
-// move the threshold run between launches), so each tile reads them from LDS
-// instead of through the query's pointers in global memory.
-struct QLds {
-  float w[kHeadsPad];
-  float lo[kHeadsPad];
-  float hi[kHeadsPad];
-  float tau_o;
-  uint32_t active;
-  uint64_t tau_id;
-  const uint32_t* subset_bits;
-};
-constexpr int kQLdsBytes = APEX_MAX_FUSED_QUERIES * (int)sizeof(QLds);
-
 // Row of accumulator v of lane half h in a 32x32 D tile.
 __host__ __device__ constexpr int d32_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
@@ -141,28 +126,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (NL == 2)
       for (int i = tid; i < (int)H2; i += T) sB2[i] = A.pd.b2[i];
     if (tid < kHeadsPad) sBo[tid] = A.pd.bo[tid];
-    if (!GATHER) {
-      // one wave per query: lanes 0..47 copy w, lo, hi; lanes 48..51 the rest.
-      // An inactive slot (a server slot without a query) may have no state:
-      // its threshold is not read.
-      for (uint32_t qi = wave; qi < A.n_queries; qi += W) {
-        const QueryDev* Q = A.queries + qi;
-        QLds* L = sQ + qi;
-        if (lane < 3 * kHeadsPad) {
-          const float* src = lane < kHeadsPad ? Q->w : lane < 2 * kHeadsPad ? Q->lo : Q->hi;
-          float* dst = lane < kHeadsPad ? L->w : lane < 2 * kHeadsPad ? L->lo : L->hi;
-          dst[lane % kHeadsPad] = src[lane % kHeadsPad];
-        } else if (lane == 48) {
-          L->tau_o = Q->active ? Q->st->tau_o : 0.0f;
-        } else if (lane == 49) {
-          L->active = Q->active;
-        } else if (lane == 50) {
-          L->tau_id = Q->active ? Q->st->tau_id : 0ull;
-        } else if (lane == 51) {
-          L->subset_bits = Q->subset_bits;
-        }
-      }
-    }
+    if (!GATHER) copy_queries_lds(A, sQ, wave, W, lane);
     if (NL == 1) {
       const uint4* src = reinterpret_cast<const uint4*>(A.pd.wo);
       uint4* dst = reinterpret_cast<uint4*>(sWo);

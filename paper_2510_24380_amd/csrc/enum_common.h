@@ -33,6 +33,44 @@ __device__ __forceinline__ float act_pre(float h) {
 // Objective of four heads, combined across groups of four in a fixed order by
 // the callers; every kernel that scores a compound uses the same order, so its
 // objective is the same bits in every kernel.
+// Epilogue parameters of one query, copied to LDS once per tile launch: the
+// threshold and the bounds do not change during a launch (the selections that
+// move the threshold run between launches), so each tile reads them from LDS
+// instead of through the query's pointers in global memory.
+struct QLds {
+  float w[kHeadsPad];
+  float lo[kHeadsPad];
+  float hi[kHeadsPad];
+  float tau_o;
+  uint32_t active;
+  uint64_t tau_id;
+  const uint32_t* subset_bits;
+};
+constexpr int kQLdsBytes = APEX_MAX_FUSED_QUERIES * (int)sizeof(QLds);
+
+// Fills sQ[0, n_queries) (one wave per query, W waves): lanes 0..47 copy w, lo
+// and hi, lanes 48..51 the rest. An inactive slot (a server slot without a
+// query) may have no state: its threshold is not read.
+__device__ __forceinline__ void copy_queries_lds(const EnumArgs& A, QLds* sQ, int wave, int W, int lane) {
+  for (uint32_t qi = wave; qi < A.n_queries; qi += W) {
+    const QueryDev* Q = A.queries + qi;
+    QLds* L = sQ + qi;
+    if (lane < 3 * kHeadsPad) {
+      const float* src = lane < kHeadsPad ? Q->w : lane < 2 * kHeadsPad ? Q->lo : Q->hi;
+      float* dst = lane < kHeadsPad ? L->w : lane < 2 * kHeadsPad ? L->lo : L->hi;
+      dst[lane % kHeadsPad] = src[lane % kHeadsPad];
+    } else if (lane == 48) {
+      L->tau_o = Q->active ? Q->st->tau_o : 0.0f;
+    } else if (lane == 49) {
+      L->active = Q->active;
+    } else if (lane == 50) {
+      L->tau_id = Q->active ? Q->st->tau_id : 0ull;
+    } else if (lane == 51) {
+      L->subset_bits = Q->subset_bits;
+    }
+  }
+}
+
 __device__ __forceinline__ float obj_partial(const float* w4, const float* h4) {
   float p = w4[0] * h4[0];
   p = fmaf(w4[1], h4[1], p);

@@ -47,7 +47,7 @@ __host__ __device__ constexpr int enum_lds_bytes(int h1, int nl, int h2, bool ga
   int region = rows > chunk ? rows : chunk;
   int wo = nl == 2 ? 16 * h2 * 4 : (nl == 1 ? 16 * h1 * 4 : 0);
   int b2 = nl == 2 ? h2 * 4 : 0;
-  return region + wo + b2;
+  return region + wo + b2 + (gather ? 0 : kHeadsPad * 4 + kQLdsBytes);  // + final bias, query parameters
 }
 
 template <int H1, int NL, int ACT, bool GATHER>
@@ -71,6 +71,8 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
   unsigned char* sWo = smem + REGION;
   const uint32_t H2 = NL == 2 ? A.H2 : 0;
   float* sB2 = reinterpret_cast<float*>(sWo + (NL == 2 ? 16 * H2 * 4 : (NL == 1 ? 16 * H1 * 4 : 0)));
+  float* sBo = sB2 + (NL == 2 ? H2 : 0);                // tile mode: final bias
+  QLds* sQ = reinterpret_cast<QLds*>(sBo + kHeadsPad);  // tile mode: one entry per query
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
   const int NC = NL == 2 ? (int)(H2 / 16) : 0;
@@ -106,6 +108,10 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
     for (int i = tid; i < wo_bytes / 16; i += T) dst[i] = src[i];
     if (NL == 2)
       for (int i = tid; i < (int)H2; i += T) sB2[i] = A.pd.b2[i];
+    if (!GATHER) {
+      if (tid < kHeadsPad) sBo[tid] = A.pd.bo[tid];
+      copy_queries_lds(A, sQ, wave, W, lane);
+    }
     // gather mode stages no rows, so no later barrier precedes the first read
     __syncthreads();
   }
@@ -313,7 +319,7 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
     }
     float heads[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) heads[q] = fmaf(hacc[q], So, A.pd.bo[4 * g + q]);
+    for (int q = 0; q < 4; ++q) heads[q] = fmaf(hacc[q], So, GATHER ? A.pd.bo[4 * g + q] : sBo[4 * g + q]);
 
     if constexpr (GATHER) {
       if (valid) {
@@ -323,17 +329,18 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
       }
     } else {
       for (uint32_t qi = 0; qi < A.n_queries; ++qi) {
-        const QueryDev* Q = A.queries + qi;
-        if (!Q->active) continue;
-        if (Q->subset_bits && !((Q->subset_bits[S.t >> 5] >> (S.t & 31)) & 1u)) continue;
-        const float tau_o = Q->st->tau_o;
-        const uint64_t tau_id = Q->st->tau_id;
+        const QLds* L = sQ + qi;
+        if (!L->active) continue;
+        if (L->subset_bits && !((L->subset_bits[S.t >> 5] >> (S.t & 31)) & 1u)) continue;
+        const QueryDev* Q = A.queries + qi;  // appends only
+        const float tau_o = L->tau_o;
+        const uint64_t tau_id = L->tau_id;
         float w4[4];
         int ok = 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          w4[q] = Q->w[4 * g + q];
-          ok &= (heads[q] >= Q->lo[4 * g + q]) & (heads[q] <= Q->hi[4 * g + q]);
+          w4[q] = L->w[4 * g + q];
+          ok &= (heads[q] >= L->lo[4 * g + q]) & (heads[q] <= L->hi[4 * g + q]);
         }
         float p = obj_partial(w4, heads);
         // combine the four lane groups: (g0 + g1) + (g2 + g3)
