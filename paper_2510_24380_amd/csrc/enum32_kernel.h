@@ -348,13 +348,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       // written here: the weight read two steps ahead, the MFMA, then this
       // step's share of the activation work.
       auto gemm = [&](int c, f32x16& acc, bool pf, const f32x16& old, int c_old, bool fin) {
-        if (pf) load_chunk(c + 1, (c + 1) & 1);
-        bf16x8 wo[2];
-        if (fin) {
-#pragma unroll
-          for (int st = 0; st < 2; ++st)
-            wo[st] = __builtin_bit_cast(bf16x8, ldb16(wor, 16u * (uint32_t)lane, (uint32_t)(c_old * 2048 + st * 1024)));
-        }
+        // The start values and the final-layer weights are requested before the
+        // next chunk's loads: the compiler cannot tell that those loads leave
+        // the start values alone, and would otherwise wait for all of them here
+        // (and, the counter being in order, for them again before the final layer).
         const float* b2c = sB2 + c * 32 + 4 * h;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -364,6 +361,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           acc[4 * q + 2] = bq.z;
           acc[4 * q + 3] = bq.w;
         }
+        bf16x8 wo[2];
+        if (fin) {
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+            wo[st] = __builtin_bit_cast(bf16x8, ldb16(wor, 16u * (uint32_t)lane, (uint32_t)(c_old * 2048 + st * 1024)));
+        }
+        if (pf) load_chunk(c + 1, (c + 1) & 1);
         const unsigned char* wc = sW + (c & 1) * CHUNK;
         Frag ring[3];
         ring[0] = load_frag<Frag>(wc + (size_t)lane * E * M::EB);
