@@ -412,10 +412,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
       };
       // the activation and final layer of one chunk on their own (last chunk)
-      auto finish = [&](int c, const f32x16& acc) {
+      // (its final-layer weights wo are requested before the chunk's GEMM)
+      auto finish = [&](const f32x16& acc, const bf16x8 (&wo_c)[2]) {
 #pragma unroll
         for (int st = 0; st < 2; ++st) {
-          const bf16x8 wo = __builtin_bit_cast(bf16x8, ldb16(wor, 16u * (uint32_t)lane, (uint32_t)(c * 2048 + st * 1024)));
+          const bf16x8 wo = wo_c[st];
           bf16x8 xb;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -437,8 +438,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         gemm(c + 1, accA, true, accB, c, true);
         publish();
       }
+      bf16x8 wo_last[2];
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+        wo_last[st] = __builtin_bit_cast(bf16x8, ldb16(wor, 16u * (uint32_t)lane, (uint32_t)(c * 2048 + st * 1024)));
       gemm(c, accB, false, accA, c - 1, true);  // c == NC - 1
-      finish(c, accB);
+      finish(accB, wo_last);
       __syncthreads();  // the region is restaged by the next tile
     }
 
