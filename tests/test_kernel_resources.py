@@ -2,11 +2,12 @@
 recorded by the build from the compiler's resource-usage remarks), and every
 instantiation fits two waves per SIMD.
 
-The BF16 kernel at the widest shape runs at the 256-register limit; there the
-compiler parks a few loop-invariant values in scratch once per tile (at most
-32 bytes per lane, reloaded once per tile, never inside the chunk loop). Any
-spilling of the loop's own state shows up as hundreds of bytes per lane (an
-earlier version spilled 960), which this bound catches."""
+The BF16 kernel at the widest shape runs at the 256-register limit; the bound
+below lets the compiler park a few loop-invariant values in scratch there (at
+most 32 bytes per lane, reloaded once per tile, never inside the chunk loop;
+the current build needs none). Any spilling of the loop's own state shows up as
+hundreds of bytes per lane (an earlier version spilled 960), which this bound
+catches."""
 import os
 
 import pytest
