@@ -30,6 +30,8 @@
  *     pointers are ordinary host memory. The library never frees caller memory
  *     and never allocates device memory: all device scratch comes from
  *     caller-provided workspaces whose size the *_workspace_size calls report.
+ *     An engine keeps a small pool of pinned host buffers for reading results
+ *     back (page-locked host memory, freed by apex_engine_destroy).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
  *     that launch work return after it has completed on that stream unless stated
  *     otherwise.
