@@ -181,6 +181,28 @@ def test_fused_batch_equals_single(mixed):
             assert np.array_equal(f.ids, single.ids) and np.array_equal(f.objective, single.objective)
 
 
+def test_fused_batch_of_32_queries(mixed):
+    """The most queries one pass fuses (32): objectives, bounds, k and reaction
+    subsets all differ; every fused answer equals the query searched alone."""
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print("case: fused batch of 32", flush=True)
+    rng = np.random.default_rng(61)
+    subsets = [None, [0, 2], [1], [3], [0, 1, 2, 3], [2, 3]]
+    qs = []
+    for i in range(32):
+        w = rng.standard_normal(15).astype(np.float32)
+        base = mixed_query(sample, 1 + int(rng.integers(0, 300)), q_hi=float(rng.uniform(0.5, 0.95)),
+                           reactions=subsets[i % len(subsets)])
+        qs.append(Query(w=w, constraints=base.constraints if i % 3 else [], k=base.k, reactions=base.reactions))
+    for prec in ("fp32", "bf16", "fp8"):
+        fused = eng.search_batch(qs, precision=prec)
+        assert len(fused) == 32
+        for i, (q, f) in enumerate(zip(qs, fused)):
+            single = eng.search(q, precision=prec)
+            assert np.array_equal(f.ids, single.ids), f"{prec} query {i}"
+            assert np.array_equal(f.objective, single.objective), f"{prec} query {i}"
+
+
 def test_ties_lower_id_wins():
     """Duplicated synthon rows give identical scores; lower ids rank first."""
     print("case: ties", flush=True)
@@ -248,12 +270,12 @@ def wide():
     the one-workgroup sort holds."""
     lib_h = g.make_library(59, [2, 2, 3], [150, 120, 90, 200, 20, 15, 12], 64)
     dec_h = g.make_decoder(59, [64, 128, 128, 5], ACT_SILU)
-    return lib_h, dec_h, device_objects(lib_h, dec_h, precisions=("fp32", "bf16"))
+    return lib_h, dec_h, device_objects(lib_h, dec_h, precisions=("fp32", "bf16", "fp8"))
 
 
 def test_answers_longer_than_one_workgroup_sort(wide):
     """k = 9000 (> 8192): the FP32 answer is ordered by the multi-workgroup rank
-    sort, and the BF16 pool (36,000 entries) is selected before that sort."""
+    sort, and the BF16 / FP8 pools (36,000 entries) are selected before that sort."""
     lib_h, dec_h, (lib, dec, eng) = wide
     sample = oracle.heads(lib_h, dec_h, np.arange(0, lib_h.n_compounds, 7, dtype=np.uint64))
     lo = float(np.float32(np.quantile(sample[:, 1], 0.3)))
@@ -262,9 +284,10 @@ def test_answers_longer_than_one_workgroup_sort(wide):
     r = eng.search(q, precision="fp32")
     ref = check_fp32_exact(lib_h, dec_h, q, r, "k=9000 fp32")
     assert ref.n_feasible > 9000
-    print("case: k=9000 bf16", flush=True)
-    r = eng.search(q, precision="bf16")
-    check_lowp(lib_h, dec_h, q, r, "k=9000 bf16")
+    for prec in ("bf16", "fp8"):
+        print(f"case: k=9000 {prec}", flush=True)
+        r = eng.search(q, precision=prec)
+        check_lowp(lib_h, dec_h, q, r, f"k=9000 {prec}")
 
 
 def test_ids_beyond_32_bits():
