@@ -7,14 +7,14 @@
 //  2. chunked enumeration: the fused kernel appends compounds whose key beats
 //     the threshold; after each chunk the select kernel compacts the buffer to
 //     the K best and raises the threshold (the chain-of-batches merge of
-//     Appendix A.8, without materialising any score array); a chunk whose
+//     Appendix A.5, without materialising any score array); a chunk whose
 //     appends overflow the buffer is dropped and re-run once the threshold is
 //     higher;
 //  3. FP32 precision: the K = k survivors are the answer. BF16/FP8: the K =
 //     pool_factor * k survivors (enumerated with bounds relaxed by a per-head
 //     margin) are rescored in FP32 with the exact bounds and the best k kept;
 //  4. rank sort by (objective desc, id asc), FP32 heads of the answer, decode of
-//     ids to (reaction, synthons) on the GPU (Appendix A.8), copy to the host.
+//     ids to (reaction, synthons) on the GPU (Appendix A.5), copy to the host.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>

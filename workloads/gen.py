@@ -11,7 +11,7 @@ variants numpy or libm pick there.
 
 The shapes follow the paper's libraries: two- and three-component reactions whose
 R-groups hold tens to thousands of synthons (Section 3.1, Appendix A.1), 28 task
-heads in the paper's probe (Appendix A.6), constraint sets of two to six one- or
+heads in the paper's probe (Appendix A.8), constraint sets of two to six one- or
 two-sided thresholds (Table "Constraint sets"). Values are N(0, 1) embeddings and
 Xavier-uniform weights, not trained models.
 """
