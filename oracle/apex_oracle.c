@@ -25,7 +25,11 @@
  *   - orc_topk_lex keeps the paper's own formulation: a size-k priority queue
  *     ordered lexicographically by (violation c, objective), where
  *     c = -sum max(0, l_i - f_i) - sum max(0, f_i - u_i), followed by removal of
- *     entries with c < 0 (Section 4.3, violation equation).
+ *     entries with c < 0 (Section 4.3, violation equation). Skipping that
+ *     removal gives the violation-ranked fallback: when fewer than k compounds
+ *     are feasible, the least-violating ones fill the remaining places.
+ *   - Values the paper does not cover: a compound whose objective or any head
+ *     is NaN or +-Inf is never a candidate (in either form).
  *
  * Everything is evaluated in double precision from the float32 inputs, by
  * plain loops: the sum of table rows in slot order, then each layer as
@@ -244,6 +248,16 @@ static double objective(const orc_query* Q, const double* heads, uint32_t H) {
   return o;
 }
 
+/* Reading of the problem statement for values it does not cover: a compound
+ * whose objective or any head is not a finite number (NaN or +-Inf) has no
+ * meaningful score and is never a candidate, whatever its bounds. */
+static int finite_compound(double o, const double* heads, uint32_t H) {
+  if (!isfinite(o)) return 0;
+  for (uint32_t h = 0; h < H; h++)
+    if (!isfinite(heads[h])) return 0;
+  return 1;
+}
+
 static int feasible(const orc_query* Q, const double* heads) {
   for (uint32_t c = 0; c < Q->n_con; c++) {
     double f = heads[Q->con_head[c]];
@@ -425,7 +439,7 @@ int orc_topk(const orc_library* L, const orc_decoder* dec, const orc_query* Q, i
           uint64_t id = offset[t] + ((uint64_t)i0 * n1 + i1) * n2 + i2;
           forward_compound(L, &D, rows, ns, x, y, heads);
           double o = objective(Q, heads, H);
-          if (o != o) continue; /* NaN objective: never returned */
+          if (!finite_compound(o, heads, H)) continue;
           if (feasible(Q, heads)) {
             vec_push(&feas[tid], id, o);
           } else if (-violation(Q, heads) <= near_tol * (double)(Q->n_con ? Q->n_con : 1)) {
@@ -512,6 +526,7 @@ int orc_topk(const orc_library* L, const orc_decoder* dec, const orc_query* Q, i
 /* The paper's literal form (Section 4.3): a size-k priority queue over       */
 /* (violation, objective) in lexicographic order, ties by lower id, then drop */
 /* entries with negative violation. Single-threaded, for small libraries.     */
+/* Without the final removal the same queue is the violation-ranked fallback. */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -526,8 +541,13 @@ static int lex_better(const lex_entry* a, const lex_entry* b) {
   return a->id < b->id;
 }
 
-int orc_topk_lex(const orc_library* L, const orc_decoder* dec, const orc_query* Q, uint64_t* out_ids,
-                 double* out_o, uint64_t* n_out) {
+/* keep_violators = 0: the paper's result (violators removed at the end).
+ * keep_violators = 1: the queue as it stands after the last compound, so that
+ * when fewer than k compounds are feasible the remaining places go to the
+ * least-violating compounds (best violation first, then objective, then id);
+ * out_c receives each entry's violation (<= 0) when it is not NULL. */
+int orc_topk_lex(const orc_library* L, const orc_decoder* dec, const orc_query* Q, int keep_violators,
+                 uint64_t* out_ids, double* out_o, double* out_c, uint64_t* n_out) {
   const uint32_t T = L->n_reactions;
   uint32_t* slot_base = (uint32_t*)malloc(sizeof(uint32_t) * (T + 1));
   uint64_t* row_base = (uint64_t*)malloc(sizeof(uint64_t) * 3 * (T + 1));
@@ -557,7 +577,7 @@ int orc_topk_lex(const orc_library* L, const orc_decoder* dec, const orc_query* 
           e.id = offset[t] + ((uint64_t)i0 * n1 + i1) * n2 + i2;
           forward_compound(L, &D, rows, ns, x, y, heads);
           e.o = objective(Q, heads, D.H);
-          if (e.o != e.o) continue;
+          if (!finite_compound(e.o, heads, D.H)) continue;
           e.c = violation(Q, heads);
           /* insert if the queue has room or e beats the worst entry */
           if (qn < Q->k || lex_better(&e, &qv[qn - 1])) {
@@ -573,9 +593,10 @@ int orc_topk_lex(const orc_library* L, const orc_decoder* dec, const orc_query* 
   }
   uint64_t m = 0;
   for (uint64_t q = 0; q < qn; q++) {
-    if (qv[q].c < 0.0) continue; /* remove violators at the end */
+    if (qv[q].c < 0.0 && !keep_violators) continue; /* remove violators at the end */
     out_ids[m] = qv[q].id;
     out_o[m] = qv[q].o;
+    if (out_c) out_c[m] = qv[q].c;
     m++;
   }
   *n_out = m;

@@ -69,7 +69,7 @@ def _load():
         lib.orc_heads.restype = ctypes.c_int
         lib.orc_topk.argtypes = [P, P, P, ctypes.c_int, ctypes.c_uint64, ctypes.c_double, P, P, P, P]
         lib.orc_topk.restype = ctypes.c_int
-        lib.orc_topk_lex.argtypes = [P, P, P, P, P, P]
+        lib.orc_topk_lex.argtypes = [P, P, P, ctypes.c_int, P, P, P, P]
         lib.orc_topk_lex.restype = ctypes.c_int
         lib.orc_max_threads.argtypes = []
         lib.orc_max_threads.restype = ctypes.c_int
@@ -201,15 +201,20 @@ def topk(lib, dec, q, extra: int = 1, near_tol: float = 0.0, nthreads: int = 0) 
                 min_violation_near=float(info.min_violation_near), n_near=int(info.n_near))
 
 
-def topk_lex(lib, dec, q):
-    """The paper's lexicographic priority-queue form; returns (ids, objective)."""
+def topk_lex(lib, dec, q, keep_violators: bool = False, with_violation: bool = False):
+    """The paper's lexicographic priority-queue form; returns (ids, objective),
+    plus each entry's violation (<= 0) when with_violation. keep_violators
+    returns the queue without the final removal of violating compounds (the
+    violation-ranked fallback)."""
     keep = _Keep()
     L = _lib_struct(lib, keep)
     D = _dec_struct(dec, keep)
     Q = _query_struct(q, len(lib.n_slots), keep)
     ids = np.zeros(max(int(q.k), 1), dtype=np.uint64)
     o = np.zeros(max(int(q.k), 1), dtype=np.float64)
+    c = np.zeros(max(int(q.k), 1), dtype=np.float64)
     n = ctypes.c_uint64(0)
-    _load().orc_topk_lex(ctypes.byref(L), ctypes.byref(D), ctypes.byref(Q), ids.ctypes.data,
-                         o.ctypes.data, ctypes.byref(n))
-    return ids[:n.value].copy(), o[:n.value].copy()
+    _load().orc_topk_lex(ctypes.byref(L), ctypes.byref(D), ctypes.byref(Q), int(bool(keep_violators)),
+                         ids.ctypes.data, o.ctypes.data, c.ctypes.data, ctypes.byref(n))
+    out = (ids[:n.value].copy(), o[:n.value].copy())
+    return out + (c[:n.value].copy(),) if with_violation else out

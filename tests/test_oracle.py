@@ -296,3 +296,120 @@ def test_generator_native_matches_numpy():
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
     z = g.normal_f32(4, "check", 400_000)
     assert abs(float(z.mean())) < 0.01 and abs(float(z.std()) - 1) < 0.01
+
+
+def _all_heads(lib, dec, q=None):
+    """(id, t, idx, heads) of every compound (of q's reactions), forward pass in
+    torch fp64, independent of the oracle's loops."""
+    out = []
+    for cid, t, idx in all_compounds(lib):
+        if q is not None and q.reactions is not None and t not in q.reactions:
+            continue
+        out.append((cid, t, idx, torch_heads(lib, dec, t, idx)))
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 7, 20, 60])
+def test_margins_brute_force(k):
+    """The margin report of orc_topk, recomputed by brute force: the smallest
+    distance of a returned compound from its nearest bound, and the smallest
+    worst-bound violation among infeasible compounds that are within near_tol of
+    feasibility and score at least the (k+1)-th feasible objective."""
+    lib = small_library(71, [2, 3], [6, 5, 3, 4, 2], 8)
+    dec = g.make_decoder(71, [8, 16, 4], ACT_SILU)
+    rows = _all_heads(lib, dec)
+    H = np.array([r[3] for r in rows])
+    q = Query(w=np.array([1.0, 0.0, -0.5, 0.0], np.float32),
+              constraints=[Constraint(1, np.float32(np.quantile(H[:, 1], 0.3)), math.inf),
+                           Constraint(3, np.float32(np.quantile(H[:, 3], 0.1)),
+                                      np.float32(np.quantile(H[:, 3], 0.85)))], k=k)
+    near_tol = 0.5
+    feas, infeas = [], []
+    for cid, _, _, h in rows:
+        o = float(np.dot(q.w.astype(np.float64), h))
+        viol = [max(float(c.lo) - h[c.head], h[c.head] - float(c.hi)) for c in q.constraints]
+        (feas if max(viol) <= 0 else infeas).append((cid, o, h, max(viol)))
+    feas.sort(key=lambda e: (-e[1], e[0]))
+    top = feas[:k]
+    slack = min(min(h[c.head] - float(c.lo), float(c.hi) - h[c.head]) for _, _, h, _ in top for c in q.constraints)
+    cut = feas[k][1] if len(feas) > k else -math.inf
+    near = [e for e in infeas if e[3] <= near_tol]
+    near_cut = [e[3] for e in near if e[1] >= cut]
+    r = oracle.topk(lib, dec, q, extra=1, near_tol=near_tol)
+    assert r.n_feasible == len(feas)
+    assert r.answer_ids.tolist() == [e[0] for e in top]
+    assert r.n_near == len(near) > 0
+    assert abs(r.min_slack_selected - slack) <= 1e-12 * max(1.0, abs(slack))
+    want = min(near_cut) if near_cut else math.inf
+    assert (r.min_violation_near == want) if math.isinf(want) else abs(r.min_violation_near - want) <= 1e-12
+    if len(feas) > k:
+        assert abs(r.gap_k - (feas[k - 1][1] - feas[k][1])) <= 1e-12
+    else:  # every feasible compound is returned: no cut, every near compound counts
+        assert math.isinf(r.gap_k) and abs(r.min_violation_near - min(e[3] for e in near)) <= 1e-12
+
+
+def nonfinite_library():
+    """Two-slot library with a linear decoder: slot-0 synthon 2 carries +Inf in a
+    column every head reads with a positive weight (its compounds get +Inf heads
+    and, with non-negative objective weights, a +Inf objective), slot-1 synthon 1
+    carries a NaN (its compounds get NaN heads)."""
+    lib = small_library(73, [2], [5, 4], 8)
+    dec = g.make_decoder(73, [8, 3], ACT_NONE)
+    dec.W[0][:, 3] = np.array([0.5, 0.3, 0.2], np.float32)
+    lib.tables[2, 3] = np.inf
+    lib.tables[5 + 1, 6] = np.nan
+    return lib, dec
+
+
+def test_nonfinite_compounds_are_never_returned():
+    """A compound whose objective or any head is NaN or +-Inf is not a
+    candidate: the answer is the finite compounds only, by (objective desc, id)."""
+    lib, dec = nonfinite_library()
+    q = Query(w=np.array([1.0, 0.5, 0.25], np.float32), constraints=[], k=100)
+    rows = _all_heads(lib, dec)
+    fin = [(cid, float(np.dot(q.w.astype(np.float64), h))) for cid, _, _, h in rows
+           if np.all(np.isfinite(h)) and np.isfinite(np.dot(q.w.astype(np.float64), h))]
+    fin.sort(key=lambda e: (-e[1], e[0]))
+    assert len(fin) == 4 * 3
+    # the +Inf compounds exist and would rank first if they were candidates
+    o_all = {cid: float(np.dot(q.w.astype(np.float64), h)) for cid, _, _, h in rows}
+    assert any(math.isinf(v) and v > 0 for v in o_all.values())
+    r = oracle.topk(lib, dec, q)
+    assert r.n_feasible == 12 and r.answer_ids.tolist() == [e[0] for e in fin]
+    ids, _ = oracle.topk_lex(lib, dec, q)
+    assert ids.tolist() == [e[0] for e in fin]
+    # with a bound on the infinite head the same compounds stay out
+    q2 = Query(w=q.w, constraints=[Constraint(0, -math.inf, math.inf)], k=100)
+    assert oracle.topk(lib, dec, q2).answer_ids.tolist() == [e[0] for e in fin]
+
+
+@pytest.mark.parametrize("k", [3, 25, 200])
+def test_violation_ranked_fallback_brute_force(k):
+    """The queue of Section 4.3 without the final removal: compounds ordered by
+    (violation desc, objective desc, id asc), where the violation is minus the
+    summed distances outside the bounds; with few feasible compounds the
+    least-violating ones follow them."""
+    lib = small_library(79, [2, 3], [5, 4, 3, 3, 2], 8)
+    dec = g.make_decoder(79, [8, 12, 12, 4], ACT_SILU)
+    rows = _all_heads(lib, dec)
+    H = np.array([r[3] for r in rows])
+    cons = [Constraint(0, np.float32(np.quantile(H[:, 0], 0.7)), math.inf),
+            Constraint(2, -math.inf, np.float32(np.quantile(H[:, 2], 0.4)))]
+    q = Query(w=np.array([0.0, 1.0, 0.0, -0.25], np.float32), constraints=cons, k=k)
+    ent = []
+    for cid, _, _, h in rows:
+        c = -sum(max(0.0, float(x.lo) - h[x.head]) + max(0.0, h[x.head] - float(x.hi)) for x in cons)
+        ent.append((c, float(np.dot(q.w.astype(np.float64), h)), cid))
+    ent.sort(key=lambda e: (-e[0], -e[1], e[2]))
+    want = ent[:k]
+    ids, o, c = oracle.topk_lex(lib, dec, q, keep_violators=True, with_violation=True)
+    assert ids.tolist() == [e[2] for e in want]
+    np.testing.assert_allclose(c, [e[0] for e in want], rtol=0, atol=1e-12)
+    n_feas = sum(1 for e in ent if e[0] == 0.0)
+    assert 0 < n_feas < 200
+    # its feasible head is the ordinary answer; violators only fill places the
+    # feasible set cannot
+    r = oracle.topk(lib, dec, q)
+    m = min(k, n_feas)
+    assert ids[:m].tolist() == r.answer_ids.tolist()
+    assert np.all(c[:m] == 0.0) and np.all(c[m:] < 0.0)
