@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const float oA = __shfl_xor(pA, 32), oB = __shfl_xor(pB, 32);
         ok &= __shfl_xor(ok, 32);
         const float o = canon_zero(h == 0 ? (pA + oA) + (pB + oB) : 0.0f);
-        const bool pass = h == 0 && valid && ok && (o == o) && key_passes(o, cid, tau_o, tau_id);
+        const bool pass = h == 0 && valid && ok && finite_obj(o) && key_passes(o, cid, tau_o, tau_id);
         const uint64_t m = __ballot(pass);
         if (m) {
           uint32_t base = 0;

@@ -81,6 +81,11 @@ __device__ __forceinline__ float obj_partial(const float* w4, const float* h4) {
 
 __device__ __forceinline__ float canon_zero(float o) { return o == 0.0f ? 0.0f : o; }
 
+// A compound is a candidate only when its objective is a finite number. The
+// objective sums every head times its weight (zero weights included, and
+// 0 * +-Inf is NaN), so it is finite exactly when every head is.
+__device__ __forceinline__ bool finite_obj(float o) { return __builtin_fabsf(o) < __builtin_inff(); }
+
 // Order-preserving map of a float to uint32 (larger float -> larger key).
 __device__ __forceinline__ uint32_t ord_f32(float o) {
   uint32_t u = __float_as_uint(o);

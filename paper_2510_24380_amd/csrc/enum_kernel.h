@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
         ok &= __shfl_xor(ok, 16);
         ok &= __shfl_xor(ok, 32);
         const float o = canon_zero(p);
-        const bool pass = g == 0 && valid && ok && (o == o) && key_passes(o, cid, tau_o, tau_id);
+        const bool pass = g == 0 && valid && ok && finite_obj(o) && key_passes(o, cid, tau_o, tau_id);
         const uint64_t mask = __ballot(pass);
         if (mask) {
           uint32_t base = 0;
@@ -371,13 +371,16 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
 }
 
 // Heads of listed compounds with a two-hidden-layer decoder, for short lists
-// (FP32 rescoring of a pool, answer heads). The tile kernel's gather mode
-// gives each wave all H2/16 weight chunks in sequence, which leaves a short
-// list with few, long-running workgroups. Here a workgroup takes 16 compounds,
-// every wave computes their layer-1 activations, wave w takes chunks w, w + 8,
-// ... (weights read from the caches), and the eight partial final-layer sums
-// are added in wave order.
-__host__ __device__ constexpr int gather_split_lds_bytes(int h2) { return 16 * h2 * 4 + h2 * 4 + kWaves16 * 64 * 16; }
+// (FP32 rescoring of a pool, answer heads, warm-start samples). The tile
+// kernel's gather mode gives each wave all H2/16 weight chunks in sequence,
+// which leaves a short list with few, long-running workgroups. Here a workgroup
+// takes 16 compounds, every wave computes their layer-1 activations, wave w
+// takes chunks w, w + 8, ... (weights read from the caches) and leaves the
+// chunks' second-layer activations in LDS; one wave then runs the final layer
+// over the chunks in order 0, 1, ..., exactly as the tile kernel does, so the
+// heads (and any objective formed from them) are the same bits as in the
+// enumeration.
+__host__ __device__ constexpr int gather_split_lds_bytes(int h2) { return 16 * h2 * 4 + h2 * 4 + h2 * 64; }
 
 template <int H1, int ACT>
 __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gather_split(
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
   const uint32_t H2 = A.H2;
   float* sWo = reinterpret_cast<float*>(smem);
   float* sB2 = sWo + 16 * H2;
-  f32x4* sRed = reinterpret_cast<f32x4*>(sB2 + H2);
+  float* sAct = sB2 + H2;  // [H2 / 4 final-layer steps][64 lanes]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
   const int NC = (int)(H2 / 16);
   const uint64_t v = (uint64_t)blockIdx.x * 16;
@@ -463,18 +466,16 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) hacc = mma16x4(wof[(c * 4 + q) * 64 + lane], act_pre<ACT>(acc[q]), hacc);
+    for (int q = 0; q < 4; ++q) sAct[(c * 4 + q) * 64 + lane] = act_pre<ACT>(acc[q]);
   }
-  sRed[wave * 64 + lane] = hacc;
   __syncthreads();
   if (wave != 0) return;
-  f32x4 h = sRed[lane];
+  // final layer in chunk order, the tile kernel's accumulation sequence
+  for (int c = 0; c < NC; ++c) {
 #pragma unroll
-  for (int w = 1; w < W; ++w) {
-    const f32x4 p = sRed[w * 64 + lane];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) h[q] += p[q];
+    for (int q = 0; q < 4; ++q) hacc = mma16x4(wof[(c * 4 + q) * 64 + lane], sAct[(c * 4 + q) * 64 + lane], hacc);
   }
+  const f32x4 h = hacc;
   const uint64_t cid = v + j;
   if (cid < A.n_ids) {
     const float So = A.pd.scal[1];

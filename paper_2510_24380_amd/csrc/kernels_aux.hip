@@ -69,6 +69,7 @@ __global__ void k_colext(const float* __restrict__ P, uint32_t h1, const uint64_
   const uint64_t r0 = slot_row0[slot];
   for (uint32_t i = 0; i < slot_size[slot]; ++i) {
     const float x = P[(r0 + i) * h1 + n];
+    if (!(__builtin_fabsf(x) < __builtin_inff())) continue;  // non-finite rows never reach an answer
     mx = fmaxf(mx, x);
     mn = fminf(mn, x);
   }
@@ -104,7 +105,7 @@ __global__ void k_actmax(const float* __restrict__ cmax, const float* __restrict
   } else {
     m = fmaxf(fabsf(hi), fabsf(lo));
   }
-  atomic_max_nonneg(out, m);
+  if (m < __builtin_inff()) atomic_max_nonneg(out, m);  // a slot without finite rows has no range
 }
 
 __global__ void k_absmax(const float* __restrict__ x, uint64_t n, float* __restrict__ out) {
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const float* __restrict
       h[4 * k4 + 3] = v.w;
     }
     o = objective16(Q->w, h);
-    bool ok = o == o;
+    bool ok = finite_obj(o);
 #pragma unroll
     for (int k = 0; k < kHeadsPad; ++k) ok = ok && h[k] >= Q->lo[k] && h[k] <= Q->hi[k];
     id = ids[i];
@@ -1134,7 +1135,8 @@ __global__ void k_head_err(const float* __restrict__ h_lp, const float* __restri
                            float* __restrict__ out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * kHeadsPad) return;
-  atomic_max_nonneg(out + (i % kHeadsPad), fabsf(h_lp[i] - h_32[i]));
+  const float e = fabsf(h_lp[i] - h_32[i]);
+  if (e < __builtin_inff()) atomic_max_nonneg(out + (i % kHeadsPad), e);  // compounds with non-finite heads never pass
 }
 
 // ---------------------------------------------------------------------------

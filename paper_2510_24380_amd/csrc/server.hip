@@ -235,15 +235,18 @@ apex_status admit(apex_server* S, SQ* q) {
     q->need[c] = 1;
     q->remaining++;
   }
-  // warm start: a sample of the whole library, scored with the query's subset
+  // warm start: a sample of the whole library, scored with the query's subset;
+  // no larger than the query's candidate buffer, which the sampled entries pass
+  // through before the selection drops them
   const int prec = (int)q->q.precision;
-  if (E->lib->total >= 8ull * S->n_sample && q->n_comp >= 8ull * S->n_sample) {
+  const uint32_t n_sample = std::min<uint32_t>(S->n_sample, q->P.cap);
+  if (E->lib->total >= 8ull * n_sample && q->n_comp >= 8ull * n_sample) {
     st = upload_active(S, {q->slot});
     if (st != APEX_OK) return st;
-    st = warm_start(E, prec, E->prec[prec].plan, E->lib->T, E->prec[prec].full_tiles, S->n_sample, S->sample_ids,
+    st = warm_start(E, prec, E->prec[prec].plan, E->lib->T, E->prec[prec].full_tiles, n_sample, S->sample_ids,
                     S->sample_heads, S->qd_dev, (uint32_t)S->qd.size(), S->s);
     if (st != APEX_OK) return st;
-    q->n_scored += S->n_sample;
+    q->n_scored += n_sample;
   }
   return APEX_OK;
 }

@@ -1,7 +1,9 @@
 """The streamed 2.9e10-compound library (2000 reactions, 5.3M synthon rows,
 5.4 GB of tables): exact FP32 parity with the FP64 oracle on a reaction subset
-of about 1e7 compounds (ids beyond 2^32), and a full-library BF16 search whose
-returned compounds are recomputed one by one in FP64."""
+of about 1e7 compounds (ids beyond 2^32), BF16 and FP8 recall@10000 on that
+subset against the stored FP64 answer with each precision's head error on 512
+stored FP64 compounds, and a full-library BF16 search whose returned compounds
+are recomputed one by one in FP64."""
 import json
 import math
 import os
@@ -35,7 +37,7 @@ def c3():
     lib = apex.Library(lib_h.n_slots, lib_h.slot_sizes, tables)
     dec = apex.Decoder(dec_h.dims, "silu", [torch.from_numpy(w).cuda() for w in dec_h.W],
                        [torch.from_numpy(b).cuda() for b in dec_h.b])
-    eng = apex.Engine(lib, dec, precisions=("fp32", "bf16"))
+    eng = apex.Engine(lib, dec, precisions=("fp32", "bf16", "fp8"))
     print("engine ready", flush=True)
     return lib_h, dec_h, lib, eng
 
@@ -46,13 +48,50 @@ def test_c3_subset_fp32_exact(c3):
     q = load_query(subset=True)
     r = eng.search(q, precision="fp32")
     k = min(q.k, gold["n_feasible"])
+    # the margins against the FP32 head error (the stored FP64 heads of 512
+    # seeded compounds against this engine's FP32 heads)
+    sample = json.load(open(os.path.join(GOLDEN, "c3_heads_sample.json")))
+    h64 = np.array(sample["heads"])
+    err32 = float(np.max(np.abs(eng.heads(np.array(sample["ids"], np.uint64), "fp32") - h64)))
+    s_o = float(np.sqrt(np.mean((h64 @ q.w.astype(np.float64)) ** 2)))
+    margin = min(gold["gap_k"], gold["min_slack_selected"], gold["min_violation_near"])
     print(f"subset of {gold['subset_compounds']} compounds: gap_k={gold['gap_k']:.3e} "
-          f"slack={gold['min_slack_selected']:.3e} near={gold['min_violation_near']:.3e}", flush=True)
+          f"slack={gold['min_slack_selected']:.3e} near={gold['min_violation_near']:.3e}; "
+          f"objective scale {s_o:.3f}, largest FP32 head error {err32:.2e}", flush=True)
+    if margin < 1e-4 * s_o:
+        print(f"boundary ambiguous at FP32 by the 1e-4 * scale rule: smallest margin {margin:.2e} is "
+              f"{margin / err32:.1f}x the largest FP32 head error", flush=True)
     assert r.ids.min() > 2 ** 32 or r.ids.max() > 2 ** 32
     assert set(r.ids.tolist()) == set(gold["ids"][:k])
     o64 = dict(zip(gold["ids"], gold["objective"]))
     ref = np.array([o64[i] for i in r.ids.tolist()])
     assert np.all(np.abs(r.objective - ref) <= 1e-5 * np.maximum(np.abs(ref), 1.0))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_c3_subset_low_precision_recall(c3, prec):
+    """recall@10000 of the low-precision search (4k pool rescored in FP32) on the
+    1e7-compound subset against the stored FP64 answer, and the per-head error
+    of that precision's enumeration arithmetic on the 512 stored compounds."""
+    lib_h, dec_h, lib, eng = c3
+    gold = json.load(open(os.path.join(GOLDEN, "c3_oracle_subset.json")))
+    sample = json.load(open(os.path.join(GOLDEN, "c3_heads_sample.json")))
+    h64 = np.array(sample["heads"])
+    err = np.abs(eng.heads(np.array(sample["ids"], np.uint64), prec) - h64)
+    print(f"{prec} head error vs FP64: max {np.round(err.max(0), 4).tolist()} mean {np.round(err.mean(0), 5).tolist()}",
+          flush=True)
+    q = load_query(subset=True)
+    print(f"case: c3 subset {prec}", flush=True)
+    r = eng.search(q, precision=prec)
+    k = min(q.k, gold["n_feasible"])
+    recall = len(set(r.ids.tolist()) & set(gold["ids"][:k])) / k
+    print(f"c3 subset {prec}: recall@{k} = {recall:.5f}, candidates {r.n_candidates}, reruns {r.n_reruns}",
+          flush=True)
+    assert len(r.ids) == k and recall >= 0.99
+    o64 = dict(zip(gold["ids"], gold["objective"]))
+    both = [i for i, x in enumerate(r.ids.tolist()) if x in o64]
+    ref = np.array([o64[x] for x in r.ids[both].tolist()])
+    assert np.all(np.abs(r.objective[both] - ref) <= 1e-5 * np.maximum(np.abs(ref), 1.0))
 
 
 def test_c3_full_bf16_pointwise(c3):

@@ -10,62 +10,14 @@ import torch
 
 import oracle
 import workloads.gen as g
-from workloads.gen import ACT_RELU, ACT_SILU, Constraint, Query
+from workloads.gen import ACT_NONE, ACT_RELU, ACT_SILU, Constraint, Query
 
 pytestmark = pytest.mark.gpu
 
+from parity import check_fp32_exact, check_lowp, lowp_recall, nonfinite_case
+
 if torch.cuda.is_available():
-    from gpu_helpers import device_objects, score_tol
-
-
-def library_scales(lib_h, dec_h, q, n=4096):
-    ids = g.sample_ids(5, "scale_sample", lib_h.n_compounds, n)
-    h = oracle.heads(lib_h, dec_h, ids)
-    return np.sqrt(np.mean(h ** 2, axis=0)), float(np.sqrt(np.mean((h @ q.w.astype(np.float64)) ** 2)))
-
-
-def check_fp32_exact(lib_h, dec_h, q, r, label):
-    ref = oracle.topk(lib_h, dec_h, q, extra=1, near_tol=1e-3)
-    k = min(q.k, ref.n_feasible)
-    print(f"[{label}] n_feasible={ref.n_feasible} gap_k={ref.gap_k:.3e} slack={ref.min_slack_selected:.3e} "
-          f"near={ref.min_violation_near:.3e}", flush=True)
-    assert len(r.ids) == k
-    # exact id set; order may differ only between compounds whose FP64
-    # objectives are closer than float32 rounding
-    assert set(r.ids.tolist()) == set(ref.answer_ids.tolist()), f"{label}: id sets differ"
-    pos = {int(i): n for n, i in enumerate(ref.answer_ids.tolist())}
-    perm = np.array([pos[int(i)] for i in r.ids.tolist()], dtype=np.int64)
-    o_ref, h_ref = ref.objective[:k][perm], ref.heads[:k][perm]
-    # tolerance 1e-5 relative, with the objective's / head's RMS over a seeded
-    # sample of the library as the floor for values near zero
-    hs, os_ = library_scales(lib_h, dec_h, q)
-    tol = score_tol(o_ref, os_)
-    assert np.all(np.abs(r.objective - o_ref) <= tol)
-    assert all(o_ref[i] >= o_ref[i + 1] - 2 * tol[i] for i in range(len(o_ref) - 1))
-    assert np.all(np.abs(r.heads - h_ref) <= 1e-5 * np.maximum(np.abs(h_ref), hs))
-    rr, ss = oracle.decode(lib_h, r.ids)
-    assert np.array_equal(rr, r.reaction) and np.array_equal(ss, r.synthon)
-    return ref
-
-
-def check_lowp(lib_h, dec_h, q, r, label, min_recall=0.99):
-    ref = oracle.topk(lib_h, dec_h, q)
-    k = min(q.k, ref.n_feasible)
-    got = set(r.ids.tolist())
-    recall = len(got & set(ref.answer_ids.tolist())) / max(k, 1)
-    print(f"[{label}] recall={recall:.4f} n={len(r.ids)} k={k}", flush=True)
-    assert recall >= min_recall
-    # every returned compound is feasible and its FP32-rescored score matches FP64
-    if len(r.ids):
-        h64 = oracle.heads(lib_h, dec_h, r.ids)
-        o64 = h64 @ q.w.astype(np.float64)
-        _, os_ = library_scales(lib_h, dec_h, q)
-        assert np.all(np.abs(r.objective - o64) <= score_tol(o64, os_))
-        for c in q.constraints:
-            assert np.all((h64[:, c.head] >= c.lo - 1e-5) & (h64[:, c.head] <= c.hi + 1e-5))
-        keys = list(zip((-r.objective).tolist(), r.ids.tolist()))
-        assert keys == sorted(keys)
-    return recall
+    from gpu_helpers import device_objects
 
 
 # ----------------------------------------------------------------------------
@@ -182,8 +134,10 @@ def test_fused_batch_equals_single(mixed):
 
 
 def test_fused_batch_of_32_queries(mixed):
-    """The most queries one pass fuses (32): objectives, bounds, k and reaction
-    subsets all differ; every fused answer equals the query searched alone."""
+    """The most queries one pass fuses (32): objectives over all 15 heads,
+    bounds, k and reaction subsets all differ. Every fused answer equals the
+    query searched alone and the FP64 oracle's answer (FP32: exact id set;
+    BF16/FP8: recall over the batch and every returned compound re-scored)."""
     lib_h, dec_h, (lib, dec, eng), sample = mixed
     print("case: fused batch of 32", flush=True)
     rng = np.random.default_rng(61)
@@ -194,13 +148,61 @@ def test_fused_batch_of_32_queries(mixed):
         base = mixed_query(sample, 1 + int(rng.integers(0, 300)), q_hi=float(rng.uniform(0.5, 0.95)),
                            reactions=subsets[i % len(subsets)])
         qs.append(Query(w=w, constraints=base.constraints if i % 3 else [], k=base.k, reactions=base.reactions))
+    assert all(np.all(q.w != 0) for q in qs)
     for prec in ("fp32", "bf16", "fp8"):
+        print(f"case: fused batch of 32 {prec}", flush=True)
         fused = eng.search_batch(qs, precision=prec)
         assert len(fused) == 32
+        hits = want = 0
         for i, (q, f) in enumerate(zip(qs, fused)):
             single = eng.search(q, precision=prec)
             assert np.array_equal(f.ids, single.ids), f"{prec} query {i}"
             assert np.array_equal(f.objective, single.objective), f"{prec} query {i}"
+            if prec == "fp32":
+                check_fp32_exact(lib_h, dec_h, q, f, f"fused fp32 query {i}")
+            else:
+                h, k = lowp_recall(lib_h, dec_h, q, f, f"fused {prec} query {i}")
+                hits, want = hits + h, want + k
+        if prec != "fp32":
+            print(f"fused {prec}: recall over the batch {hits}/{want}", flush=True)
+            assert hits >= 0.99 * want
+
+
+def test_objective_bits_equal_listed_heads(mixed):
+    """With w = e_h the objective of every returned compound is its head h, and
+    the listed-compound kernels (warm-start sample, rescoring, answer heads) give
+    the same bits as the enumeration that found it."""
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    for prec in ("fp32", "bf16", "fp8"):
+        for h in (0, 6, 14):
+            print(f"case: objective = head {h} {prec}", flush=True)
+            q = Query(w=np.eye(15, dtype=np.float32)[h], constraints=[], k=400)
+            r = eng.search(q, precision=prec)
+            heads = eng.heads(r.ids, "fp32")
+            assert np.array_equal(r.objective.view(np.uint32), (heads[:, h] + 0.0).astype(np.float32).view(np.uint32))
+            assert np.array_equal(r.heads.view(np.uint32), heads.view(np.uint32))
+            if prec == "fp32":
+                check_fp32_exact(lib_h, dec_h, q, r, f"objective = head {h}")
+
+
+@pytest.mark.parametrize("dims,act", [([8, 3], ACT_NONE), ([16, 128, 64, 3], ACT_SILU)], ids=["linear", "mlp"])
+def test_nonfinite_compounds_never_returned(dims, act):
+    """Table rows holding +Inf or NaN make their compounds' heads non-finite;
+    such compounds are never returned (the oracle's rule), in every precision,
+    and the low-precision calibration ignores them."""
+    lib_h, dec_h, q = nonfinite_case(dims, act)
+    precs = ("fp32",) if len(dims) == 2 else ("fp32", "bf16", "fp8")
+    lib, dec, eng = device_objects(lib_h, dec_h, precisions=precs)
+    ref = oracle.topk(lib_h, dec_h, q)
+    for prec in precs:
+        print(f"case: non-finite rows {dims} {prec}", flush=True)
+        r = eng.search(q, precision=prec)
+        assert np.all(np.isfinite(r.objective)) and np.all(np.isfinite(r.heads))
+        if prec == "fp32":
+            check_fp32_exact(lib_h, dec_h, q, r, f"non-finite {prec}")
+        else:
+            check_lowp(lib_h, dec_h, q, r, f"non-finite {prec}")
+        assert len(r.ids) == min(q.k, ref.n_feasible)
 
 
 def test_ties_lower_id_wins():
