@@ -188,6 +188,24 @@ apex_status apex_query_workspace_size(const apex_engine* eng, const apex_query* 
 apex_status apex_search(apex_engine* eng, const apex_query* q, void* workspace, size_t workspace_bytes,
                         void* stream, apex_result* result);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): apex_search without a workspace
+ * argument. Its device scratch is a static array of APEX_STATIC_SCRATCH_BYTES
+ * inside the library, one per GPU, resident from the first call on that GPU
+ * until the process ends; the results are read back through ordinary
+ * (pageable) host memory. It calls no hipMalloc, hipFree, hipHostMalloc or
+ * other device or pinned allocator. The engine's device must be current.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (from several threads or streams) race and must be serialised by the caller.
+ * Each call initialises everything it reads, so the contents left by the
+ * previous call do not matter. Results equal apex_search's for the same query.
+ * Errors: as apex_search, plus APEX_E_NOMEM when the query's workspace
+ * (apex_query_workspace_size) exceeds APEX_STATIC_SCRATCH_BYTES (roughly
+ * k <= 2e4 in FP32, k <= 3e3 in BF16/FP8 with the default pool) and
+ * APEX_E_INVALID when the current device is not the engine's. */
+#define APEX_STATIC_SCRATCH_BYTES (64u << 20)
+apex_status apex_search_noalloc(apex_engine* eng, const apex_query* q, void* stream, apex_result* result);
+
 /* Several queries fused into one pass over the library: the combine and the
  * decoder run once per compound, the objective, bounds and selection once per
  * query. All queries must use the same precision; n <= APEX_MAX_FUSED_QUERIES.

@@ -85,6 +85,7 @@ _SIGS = {
     "apex_engine_destroy": [P],
     "apex_query_workspace_size": [P, P, P],
     "apex_search": [P, P, P, ctypes.c_size_t, P, P],
+    "apex_search_noalloc": [P, P, P, P],
     "apex_batch_workspace_size": [P, P, U32, P],
     "apex_search_batch": [P, P, U32, P, ctypes.c_size_t, P, P],
     "apex_engine_profile": [P, ctypes.c_int, P, P, P],
@@ -299,6 +300,15 @@ class Engine:
             r.c = rc
             out.append(r.result())
         return out
+
+    def search_noalloc(self, q, precision: str = "fp32", pool_factor: int = 0,
+                       stream: Optional[torch.cuda.Stream] = None) -> SearchResult:
+        """apex_search_noalloc: the same search with the library's static device
+        scratch instead of a workspace (nothing is allocated by the call)."""
+        m = _QueryMarshal(q, self.n_heads, precision, pool_factor)
+        r = _ResultMarshal(int(q.k), self.n_heads)
+        _check(lib().apex_search_noalloc(self.handle, ctypes.byref(m.c), _stream_ptr(stream), ctypes.byref(r.c)))
+        return r.result()
 
     def heads(self, ids, precision: str = "fp32", stream: Optional[torch.cuda.Stream] = None) -> np.ndarray:
         """Heads of the listed compounds in one precision's enumeration arithmetic."""

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 #include "launch.h"
@@ -146,7 +147,12 @@ void out_layout(Bump& b, QPlan& p) {
   p.out_bytes = b.off - off0;
 }
 
-Readback::Readback(apex_engine* E, size_t bytes) : E_(E), bytes_(bytes) {
+Readback::Readback(apex_engine* E, size_t bytes, bool pageable) : E_(E), bytes_(bytes) {
+  if (pageable) {
+    host_.resize(bytes);
+    p_ = host_.data();
+    return;
+  }
   {
     std::lock_guard<std::mutex> lk(E->pin_mu);
     for (size_t i = 0; i < E->pin_free.size(); ++i)
@@ -450,7 +456,7 @@ void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& 
 }  // namespace
 
 static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq, void* ws, size_t ws_bytes,
-                              hipStream_t s, apex_result* res) {
+                              hipStream_t s, apex_result* res, bool pageable_readback = false) {
   if (!E || !qs || !res || nq == 0) return set_error(APEX_E_INVALID, "null argument");
   if (nq > APEX_MAX_FUSED_QUERIES) return set_error(APEX_E_INVALID, "%u queries > %d", nq, APEX_MAX_FUSED_QUERIES);
   for (uint32_t i = 0; i < nq; ++i) {
@@ -529,7 +535,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   // which case those chunks are re-run and the answers enqueued again
   const char* base = P[0].out;
   const size_t span = (size_t)((P[nq - 1].out + P[nq - 1].out_bytes) - base);
-  Readback rb(E, span);
+  Readback rb(E, span, pageable_readback);
   uint32_t reruns = 0;
   for (int round = 0;; ++round) {
     for (uint32_t i = 0; i < nq; ++i) {
@@ -621,4 +627,51 @@ extern "C" apex_status apex_engine_profile(apex_engine* eng, int enable, double*
   eng->prof_launches = 0;
   eng->prof_compounds = 0;
   return APEX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free search: the query's scratch is a file-scope device array,
+// one copy per GPU, held until the process ends. Host code never passes the
+// array's name to a kernel or a copy (on the host it only names a stand-in);
+// it uses the device address hipGetSymbolAddress reports for the current
+// device, looked up once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[APEX_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+apex_status static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_error(APEX_E_UNSUPPORTED, "device %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(APEX_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return APEX_OK;
+}
+}  // namespace
+
+extern "C" apex_status apex_search_noalloc(apex_engine* eng, const apex_query* q, void* stream, apex_result* result) {
+  if (!eng || !q || !result) return set_error(APEX_E_INVALID, "null argument");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != eng->device)
+    return set_error(APEX_E_INVALID, "current device %d is not the engine's device %d", dev, eng->device);
+  size_t need = 0;
+  apex_status st = apex_query_workspace_size(eng, q, &need);
+  if (st != APEX_OK) return st;
+  if (need > APEX_STATIC_SCRATCH_BYTES)
+    return set_error(APEX_E_NOMEM, "query needs %zu bytes of scratch, more than the static %zu (use apex_search)",
+                     need, (size_t)APEX_STATIC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  st = static_scratch(dev, &ws);
+  if (st != APEX_OK) return st;
+  return run_search(eng, q, 1, ws, APEX_STATIC_SCRATCH_BYTES, (hipStream_t)stream, result, true);
 }

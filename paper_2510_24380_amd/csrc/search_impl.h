@@ -89,10 +89,11 @@ const uint32_t* out_flags(const QPlan& P, const char* host, const char* base);
 void finish_read(const apex_engine* E, const QPlan& P, const char* host, const char* base, apex_result* res);
 
 // A pinned host buffer from the engine's pool (ordinary host memory if pinning
-// fails), returned to the pool on destruction.
+// fails), returned to the pool on destruction. With pageable = true it is
+// ordinary host memory and nothing is pinned.
 class Readback {
  public:
-  Readback(apex_engine* E, size_t bytes);
+  Readback(apex_engine* E, size_t bytes, bool pageable = false);
   ~Readback();
   Readback(const Readback&) = delete;
   Readback& operator=(const Readback&) = delete;
