@@ -61,7 +61,8 @@ enum { APEX_PREC_FP32 = 0, APEX_PREC_BF16 = 1, APEX_PREC_FP8 = 2 };
 #define APEX_PREC_MASK(p) (1u << (p))
 
 /* Limits of this library. */
-#define APEX_MAX_HEADS 16        /* decoder output width H */
+#define APEX_MAX_HEADS 32        /* decoder output width H of a one-layer (linear-probe) decoder */
+#define APEX_MAX_MLP_HEADS 16    /* decoder output width H with hidden layers */
 #define APEX_MAX_CONSTRAINTS 16  /* bounds per query */
 #define APEX_MAX_FUSED_QUERIES 32
 
@@ -112,12 +113,17 @@ typedef struct {
 
 /* Keeps non-owning references to the weights until every engine using the
  * decoder has been created (engines copy what they need). Supported shapes
- * (else APEX_E_UNSUPPORTED): H = dims[n_layers] <= APEX_MAX_HEADS; with two or
- * three layers the first hidden width dims[1] is 128, 256 or 512, and with three
- * layers the second hidden width dims[2] is a multiple of 32 up to 512. One
- * layer is the paper's linear probe: every head is a sum of per-synthon
- * contributions plus its bias (eq. "apex"); such engines run in FP32 only (no
- * matrix layer is left after the first layer is applied per synthon). Errors:
+ * (else APEX_E_UNSUPPORTED): H = dims[n_layers] <= APEX_MAX_HEADS with one
+ * layer and <= APEX_MAX_MLP_HEADS with two or three; with two or three layers
+ * the first hidden width dims[1] is 128, 256 or 512, and with three layers the
+ * second hidden width dims[2] is a multiple of 32 up to 512. One layer is the
+ * paper's linear probe (the 28-head LinearProbe of Appendix A.8 fits): every
+ * head is a sum of per-synthon scalar contributions plus its bias (eq. "apex"),
+ * and the search runs the paper's scalar-contribution enumeration (Appendix
+ * A.5): per query, every synthon row's objective contribution and constrained
+ * head values are formed once, then each compound costs one add and one
+ * compare on its objective. Such engines run in FP32 only (no matrix layer is
+ * left after the first layer is applied per synthon). Errors:
  * APEX_E_INVALID for NULL pointers, n_layers outside 1..3, a zero width or an
  * unknown activation. */
 apex_status apex_decoder_create(const apex_decoder_desc* desc, apex_decoder** out);
@@ -251,9 +257,10 @@ apex_status apex_server_destroy(apex_server* srv);
 
 /* Heads of listed compounds, evaluated with the enumeration arithmetic of one
  * precision (FP32, or BF16/FP8 before rescoring): the per-slot rows are
- * combined in FP32 and the decoder runs on MFMA. ids: device [n] compound ids;
- * heads: device [n x 16] FP32, columns >= H are 0; an id >= the library size
- * yields a row of NaN. Asynchronous on `stream`. Errors: APEX_E_INVALID (NULL
+ * combined in FP32 and the decoder runs on MFMA (a one-layer decoder: the
+ * synthons' contributions are summed in slot order). ids: device [n] compound
+ * ids; heads: device [n x S] FP32 with S = 16 when H <= 16 and 32 otherwise,
+ * columns >= H are 0; an id >= the library size yields a row of NaN. Asynchronous on `stream`. Errors: APEX_E_INVALID (NULL
  * pointers, precision not enabled), APEX_E_DEVICE. */
 apex_status apex_engine_heads(apex_engine* eng, const uint64_t* ids, uint32_t n, uint32_t precision, float* heads,
                               void* stream);

@@ -313,7 +313,8 @@ class Engine:
     def heads(self, ids, precision: str = "fp32", stream: Optional[torch.cuda.Stream] = None) -> np.ndarray:
         """Heads of the listed compounds in one precision's enumeration arithmetic."""
         ids_d = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int64)).cuda()
-        out = torch.empty((max(len(ids), 1), 16), dtype=torch.float32, device="cuda")
+        stride = 16 if self.n_heads <= 16 else 32  # row stride of apex_engine_heads
+        out = torch.empty((max(len(ids), 1), stride), dtype=torch.float32, device="cuda")
         _check(lib().apex_engine_heads(self.handle, ids_d.data_ptr(), len(ids), PREC[precision], out.data_ptr(),
                                        _stream_ptr(stream)))
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()

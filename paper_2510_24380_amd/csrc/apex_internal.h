@@ -18,9 +18,14 @@ constexpr uint32_t kSelectThreads = 1024;
 // each (two A-rows, 16 B-rows), small enough in LDS for two workgroups per CU.
 constexpr int kWaves16 = 8, kTileA16 = 8;  // FP32 kernel: 8 waves, one A-row each
 constexpr int kTileB = 16;
+// Linear-probe engines (one decoder layer) run the scalar-contribution kernel
+// instead: a tile is 64 "A" rows against 64 "B" rows, one wave, a lane per B
+// row. Such engines have up to kScalarHeads heads.
+constexpr int kScalarTA = 64, kScalarTB = 64;
+constexpr int kScalarHeads = 32;
 
-inline int tile_ta(int) { return 8; }
-inline int tile_tb(int) { return kTileB; }
+inline int tile_ta(bool scalar) { return scalar ? kScalarTA : 8; }
+inline int tile_tb(bool scalar) { return scalar ? kScalarTB : kTileB; }
 inline int enum_waves(int prec) { return prec == APEX_PREC_FP32 ? 8 : 4; }
 // blocks of 16 compounds per wave
 inline int enum_rows(int prec) { return prec == APEX_PREC_FP32 ? 1 : 2; }
@@ -86,6 +91,22 @@ struct SelScratch {
   uint64_t br_id[kSelBracket];
 };
 
+// Query of a linear-probe engine (Section 4.3, eq. "apex"): the objective and
+// every constrained head are sums of per-synthon contributions, so the query is
+// evaluated from per-row tables built once per query: column 0 holds each
+// synthon row's objective contribution sum_h w[h] v[h] (NaN if a head of the
+// row is not finite), column 1 + c the row's value of constrained head head[c].
+struct ScalarQuery {
+  float w[kScalarHeads];
+  uint32_t head[APEX_MAX_CONSTRAINTS];  // distinct constrained heads
+  float lo[APEX_MAX_CONSTRAINTS];       // intersected inclusive bounds per head
+  float hi[APEX_MAX_CONSTRAINTS];
+  uint32_t n_ch;                        // constrained heads
+  uint32_t pad;
+  float* tab;                           // [1 + n_ch][rows]
+  uint64_t rows;
+};
+
 // Query parameters for the fused kernel and the scoring kernels.
 struct QueryDev {
   float w[kHeadsPad];
@@ -103,6 +124,7 @@ struct QueryDev {
   uint32_t hwm;          // compaction trigger
   uint32_t active;       // 0: skip this query in a pass
   SelScratch* sel;       // selection scratch
+  const ScalarQuery* sq; // linear-probe engines: the query's per-row tables
 };
 
 struct EnumArgs {

@@ -159,6 +159,8 @@ extern "C" apex_status apex_decoder_create(const apex_decoder_desc* desc, apex_d
     if (!desc->W[l] || !desc->b[l]) return set_error(APEX_E_INVALID, "layer %u has a null pointer", l);
   const uint32_t H = desc->dims[L];
   if (H > APEX_MAX_HEADS) return set_error(APEX_E_UNSUPPORTED, "H = %u > %d heads", H, APEX_MAX_HEADS);
+  if (L >= 2 && H > APEX_MAX_MLP_HEADS)
+    return set_error(APEX_E_UNSUPPORTED, "H = %u > %d heads for a decoder with hidden layers", H, APEX_MAX_MLP_HEADS);
   const uint32_t h1 = desc->dims[1];
   if (L >= 2 && h1 != 128 && h1 != 256 && h1 != 512)
     return set_error(APEX_E_UNSUPPORTED, "first hidden width %u (128, 256 or 512 supported)", h1);
@@ -201,9 +203,10 @@ float act_prescale(uint32_t act) { return act == APEX_ACT_SILU ? -1.442695040888
 
 int elem_bytes(int p) { return p == APEX_PREC_FP32 ? 4 : (p == APEX_PREC_BF16 ? 2 : 1); }
 
-// Width of the hoisted rows: the first hidden layer, or the 16 padded heads of a
-// one-layer (linear) decoder.
-uint32_t hoist_width(const apex_decoder* D) { return D->L == 1 ? (uint32_t)kHeadsPad : D->dims[1]; }
+// Width of the hoisted rows: the first hidden layer, or, for a one-layer
+// (linear-probe) decoder, the heads padded to 16 (32 above 16 heads).
+uint32_t heads_stride(uint32_t H) { return H <= (uint32_t)kHeadsPad ? (uint32_t)kHeadsPad : (uint32_t)kScalarHeads; }
+uint32_t hoist_width(const apex_decoder* D) { return D->L == 1 ? heads_stride(D->dims[1]) : D->dims[1]; }
 
 void engine_layout(apex_engine* E, const apex_library* L, const apex_decoder* D, uint32_t mask, Bump& b) {
   const uint32_t H1 = hoist_width(D);
@@ -252,9 +255,9 @@ void engine_layout(apex_engine* E, const apex_library* L, const apex_decoder* D,
 
 // Tile plan: the selected reactions in order, with their first tile and first
 // compound in the pass.
-void apex::build_plan(const apex_library* L, int prec, const std::vector<uint32_t>& reactions,
+void apex::build_plan(const apex_library* L, bool scalar, const std::vector<uint32_t>& reactions,
                       std::vector<SelDev>& plan, uint64_t* n_tiles, uint64_t* n_compounds) {
-  const uint32_t TA = tile_ta(prec), TB = tile_tb(prec);
+  const uint32_t TA = tile_ta(scalar), TB = tile_tb(scalar);
   plan.clear();
   uint64_t tiles = 0, comps = 0;
   for (uint32_t t : reactions) {
@@ -292,6 +295,10 @@ extern "C" apex_status apex_engine_workspace_size(const apex_library* lib, const
 apex_status apex::engine_gather(apex_engine* E, int prec, const uint64_t* ids, uint32_t n, float* heads,
                                 hipStream_t s) {
   if (n == 0) return APEX_OK;
+  if (E->scalar) {
+    HIP_TRY(launch_lin_heads(E->P, E->HS, E->react, E->lib->T, E->lib->total, ids, n, heads, s));
+    return APEX_OK;
+  }
   const PrecState& S = E->prec[prec];
   EnumArgs a{};
   a.P = E->P;
@@ -322,6 +329,8 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
   hipStream_t s = (hipStream_t)stream;
   auto* E = new apex_engine();
   E->lib = lib;
+  E->scalar = dec->L == 1;
+  E->HS = E->scalar ? heads_stride(dec->dims[1]) : (uint32_t)kHeadsPad;
   E->H1 = hoist_width(dec);
   E->H2 = dec->L == 3 ? dec->dims[2] : 0;
   E->NL = dec->L - 1;
@@ -435,17 +444,21 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
     S.dev.scal = S.scal;
     S.dev.delta = S.herr;
     std::vector<SelDev> plan;
-    build_plan(lib, p, all, plan, &S.full_tiles, &S.full_compounds);
+    build_plan(lib, E->scalar, all, plan, &S.full_tiles, &S.full_compounds);
     he = up(S.plan, plan.data(), sizeof(SelDev) * plan.size());
-    if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, false, S.h2k, &S.wg_per_cu);
-    if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, true, S.h2k, nullptr);
+    if (E->scalar) {
+      if (he == hipSuccess) he = scan_prepare(&S.wg_per_cu);
+    } else {
+      if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, false, S.h2k, &S.wg_per_cu);
+      if (he == hipSuccess) he = enum_prepare(p, E->H1, E->NL, (int)E->act, true, S.h2k, nullptr);
+    }
     if (he != hipSuccess) return fail(set_error(APEX_E_DEVICE, "kernel setup: %s", hipGetErrorString(he)));
     if (S.wg_per_cu < 1) return fail(set_error(APEX_E_UNSUPPORTED, "fused kernel does not fit on a CU"));
   }
 
   // Low-precision relaxation: largest |head error| against FP32 over a
-  // stratified sample of the library.
-  const uint32_t ncal = (uint32_t)std::min<uint64_t>(kCalSamples, lib->total);
+  // stratified sample of the library (linear-probe engines are FP32 only).
+  const uint32_t ncal = E->scalar ? 0u : (uint32_t)std::min<uint64_t>(kCalSamples, lib->total);
   he = launch_sample_ids(E->prec[APEX_PREC_FP32].plan, T, E->react, lib->total, ncal, 0x5eed1234ull, E->cal_ids, s);
   if (he != hipSuccess) return fail(set_error(APEX_E_DEVICE, "calibration sample: %s", hipGetErrorString(he)));
   st = engine_gather(E, APEX_PREC_FP32, E->cal_ids, ncal, E->cal_h32, s);

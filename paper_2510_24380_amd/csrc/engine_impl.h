@@ -52,6 +52,10 @@ struct PrecState {
 struct apex_engine {
   apex_library* lib = nullptr;
   uint32_t H1 = 0, H2 = 0, NL = 0, H = 0, act = 0;  // H2: the decoder's second hidden width
+  // one-layer (linear-probe) decoder: FP32 searches run the scalar-contribution
+  // kernel; HS is the row stride of every heads array (16, or 32 above 16 heads)
+  bool scalar = false;
+  uint32_t HS = apex::kHeadsPad;
   float c_act = 1.0f;
   std::vector<uint32_t> dims;
   uint32_t mask = 0, user_mask = 0;
@@ -96,7 +100,7 @@ struct apex_engine {
 
 namespace apex {
 apex_status set_error(apex_status s, const char* fmt, ...);
-void build_plan(const apex_library* L, int prec, const std::vector<uint32_t>& reactions, std::vector<SelDev>& plan,
+void build_plan(const apex_library* L, bool scalar, const std::vector<uint32_t>& reactions, std::vector<SelDev>& plan,
                 uint64_t* n_tiles, uint64_t* n_compounds);
 apex_status engine_gather(apex_engine* E, int prec, const uint64_t* ids, uint32_t n, float* heads, hipStream_t s);
 }  // namespace apex

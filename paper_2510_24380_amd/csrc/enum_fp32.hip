@@ -23,8 +23,6 @@ namespace apex {
 
 // Gathers with two hidden layers use k_gather_split (below), not this kernel.
 const void* enum_kernel_fp32(int h1, int nl, int act, bool gather) {
-  if (nl == 0 && h1 == 16 && act == APEX_ACT_NONE)  // one-layer (linear) decoder
-    return gather ? APEX_K(16, 0, APEX_ACT_NONE, true) : APEX_K(16, 0, APEX_ACT_NONE, false);
   if (gather) { APEX_H1S_GATHER } else { APEX_H1S(false) }
   return nullptr;
 }

@@ -230,14 +230,8 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
     // ---------------- decoder layers on MFMA ----------------
     f32x4 hacc = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    if constexpr (NL == 0) {
-      // One-layer decoder (the paper's linear probe, eq. "apex"): the hoisted rows
-      // are the per-synthon head contributions (bias on slot 0), so their sum is
-      // the heads; lane group g holds heads 4 g .. 4 g + 3.
-      static_assert(H1 == 16, "linear decoder: 16 padded heads");
-#pragma unroll
-      for (int q = 0; q < 4; ++q) hacc[q] = X[q];
-    } else if constexpr (NL == 1) {
+    static_assert(NL >= 1, "the linear decoder runs in the scalar-contribution kernel");
+    if constexpr (NL == 1) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) hacc = mma16x4(load_frag<float>(sWo + (size_t)(s * 64 + lane) * 4), X[s], hacc);
     } else {

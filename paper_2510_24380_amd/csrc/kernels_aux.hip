@@ -1279,13 +1279,14 @@ hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t
 
 hipError_t launch_sample_ids(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t total, uint32_t n,
                              uint64_t seed, uint64_t* ids, hipStream_t s) {
+  if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sample_ids, dim3((n + 255) / 256), dim3(256), 0, s, sel, n_sel, react, total, n, seed, ids);
   return hipGetLastError();
 }
 
 hipError_t launch_sample_tiles(const SelDev* sel, uint32_t n_sel, const ReactDev* react, uint64_t n_tiles, uint32_t n,
                                uint64_t seed, uint64_t* ids, hipStream_t s) {
-  if (tile_ta(0) != 8) return hipErrorInvalidValue;  // two of a tile's eight first-slot rows
+  if (tile_ta(false) != 8) return hipErrorInvalidValue;  // two of a tile's eight first-slot rows
   hipLaunchKernelGGL(k_sample_tiles, dim3((n + 255) / 256), dim3(256), 0, s, sel, n_sel, react, n_tiles, n, seed, ids);
   return hipGetLastError();
 }

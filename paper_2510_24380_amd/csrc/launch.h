@@ -54,4 +54,24 @@ hipError_t launch_sample_ids(const SelDev* sel, uint32_t n_sel, const ReactDev* 
                              uint64_t seed, uint64_t* ids, hipStream_t s);
 hipError_t launch_head_err(const float* h_lp, const float* h_32, uint32_t n, float* out, hipStream_t s);
 
+// Linear-probe path (scalar.hip): per-query row tables, enumeration, scoring of
+// listed compounds, FP32 heads of listed compounds (row stride hs).
+hipError_t launch_qtab(const float* V, uint32_t hs, uint64_t rows, uint32_t H, const ScalarQuery* sq, hipStream_t s);
+hipError_t scan_prepare(int* max_wg_per_cu);
+hipError_t launch_scan(const EnumArgs& a, uint32_t grid_max, hipStream_t s);
+hipError_t launch_scan_list(const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq, const ReactDev* react,
+                            uint32_t n_react, uint64_t n_total, hipStream_t s);
+hipError_t launch_lin_heads(const float* V, uint32_t hs, const ReactDev* react, uint32_t n_react, uint64_t n_total,
+                            const uint64_t* ids, uint32_t n, float* heads, hipStream_t s);
+
+// Radix sort (radix_sort.hip) of min(st->count, n_max) entries (src_o, src_id) by
+// (objective desc, id asc); the first min(that, n_out) go to (out_o, out_id).
+// a_*/b_*: two scratch pairs of n_max entries, distinct from the source and the
+// output; hist: radix_hist_words(n_max) uint32; id_bytes: bytes of the largest id.
+uint32_t radix_blocks(uint32_t n_max);
+inline size_t radix_hist_words(uint32_t n_max) { return (size_t)256 * radix_blocks(n_max) + 256; }
+hipError_t launch_radix_sort(const QState* st, uint32_t n_max, const float* src_o, const uint64_t* src_id,
+                             uint32_t* a_k, uint64_t* a_id, uint32_t* b_k, uint64_t* b_id, float* out_o,
+                             uint64_t* out_id, uint32_t n_out, uint32_t id_bytes, uint32_t* hist, hipStream_t s);
+
 }  // namespace apex

@@ -1,0 +1,272 @@
+// The paper's own search path for a linear probe (Section 4.3, eq. "apex";
+// Appendix A.5): every head of a compound is the sum of its synthons' scalar
+// contributions v_{i,r,s} (the hoisted rows of a one-layer decoder, bias on
+// slot 0), so a query's objective and constrained heads are sums of per-row
+// scalars. Per query, one pass over the synthon rows builds those scalars
+// (k_qtab); the enumeration then spends one add and one compare per compound
+// on the objective (k_scan), and evaluates the constrained heads only for
+// compounds whose objective reaches the query's threshold.
+//
+// Arithmetic shared by every kernel here, so that a compound's objective and
+// heads are the same bits wherever they are computed: a row's objective
+// contribution is fma-accumulated over heads 0..H-1 in order; a compound's
+// value is (slot 0 + slot 1) + slot 2 for three slots and slot 0 + slot 1 for
+// two, in FP32.
+#include "enum_common.h"
+#include "launch.h"
+
+namespace apex {
+
+// ---------------------------------------------------------------------------
+// Per-query row tables.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_qtab(const float* __restrict__ V, uint32_t hs, uint64_t rows, uint32_t H,
+                                              const ScalarQuery* __restrict__ sq) {
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const float* v = V + r * hs;
+  float o = 0.0f;
+  bool fin = true;
+  for (uint32_t h = 0; h < H; ++h) {
+    const float x = v[h];
+    fin = fin && finite_obj(x);
+    o = fmaf(sq->w[h], x, o);
+  }
+  float* tab = sq->tab;
+  tab[r] = fin ? o : __builtin_nanf("");
+  const uint32_t nch = sq->n_ch;
+  for (uint32_t c = 0; c < nch; ++c) tab[(uint64_t)(c + 1) * rows + r] = v[sq->head[c]];
+}
+
+// ---------------------------------------------------------------------------
+// Helpers
+// ---------------------------------------------------------------------------
+// Table value of the A side (slot 0, or slots 0 and 1) of assignment a.
+__device__ __forceinline__ float a_value(const float* __restrict__ col, const ReactDev& R, uint32_t a) {
+  if (R.three) {
+    const uint32_t i0 = a / R.n1, i1 = a - i0 * R.n1;
+    return col[R.row0 + i0] + col[R.row1 + i1];
+  }
+  return col[R.row0 + a];
+}
+
+// Every constrained head of compound (a, b) within its bounds.
+__device__ __forceinline__ bool scalar_feasible(const ScalarQuery* __restrict__ sq, const ReactDev& R, uint32_t a,
+                                                uint32_t b) {
+  const uint32_t nch = sq->n_ch;
+  const uint64_t rows = sq->rows;
+  bool ok = true;
+  for (uint32_t c = 0; c < nch && ok; ++c) {
+    const float* col = sq->tab + (uint64_t)(c + 1) * rows;
+    const float h = a_value(col, R, a) + col[R.rowB + b];
+    ok = h >= sq->lo[c] && h <= sq->hi[c];
+  }
+  return ok;
+}
+
+// Wave-uniform copies of values every lane holds alike (tile and query
+// metadata), so the tile loop's control flow and addresses stay scalar.
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
+}
+__device__ __forceinline__ float unif(float x) { return __uint_as_float(uni32(__float_as_uint(x))); }
+template <class T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
+// Appends (o, id) of the lanes with pass set: one atomic per wave.
+__device__ __forceinline__ void wave_append(const QueryDev& Q, bool pass, float o, uint64_t id, int lane) {
+  const uint64_t m = __ballot(pass);
+  if (!m) return;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(&Q.st->count, (uint32_t)__popcll(m));
+  base = __shfl(base, 0);
+  if (pass) {
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t idx = base + (uint32_t)__popcll(m & below);
+    if (idx < Q.cap) {
+      Q.cand_o[idx] = o;
+      Q.cand_id[idx] = id;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Enumeration. One wave per tile of 64 A rows x 64 B rows; lane l holds B row
+// b0 + l in a register and takes the tile's A values one at a time from a
+// wave-private LDS row (a broadcast read). Per compound: one add and one max;
+// a group of 16 A rows whose best sum reaches the threshold is re-run with the
+// exact key order, the bounds and the append.
+// ---------------------------------------------------------------------------
+constexpr int kScanWaves = 4;
+constexpr int kScanGroup = 16;
+
+__global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
+  __shared__ __attribute__((aligned(16))) float sA[kScanWaves][kScalarTA];
+  const int lane = threadIdx.x & 63, wave = (int)uni32(threadIdx.x >> 6);
+  const uint64_t stride = (uint64_t)gridDim.x * kScanWaves;
+  float* row = sA[wave];
+  for (uint64_t v = A.tile_begin + (uint64_t)blockIdx.x * kScanWaves + wave; v < A.tile_end; v += stride) {
+    SelDev S = A.sel[find_sel(A.sel, A.n_sel, v)];
+    S.tile_start = uni64(S.tile_start);
+    S.t = uni32(S.t);
+    S.tiles_b = uni32(S.tiles_b);
+    ReactDev R = A.react[S.t];
+    R.id_off = uni64(R.id_off);
+    R.row0 = uni32(R.row0);
+    R.row1 = uni32(R.row1);
+    R.rowB = uni32(R.rowB);
+    R.n1 = uni32(R.n1);
+    R.nA = uni32(R.nA);
+    R.nB = uni32(R.nB);
+    R.three = uni32(R.three);
+    const uint64_t lt = v - S.tile_start;
+    const uint32_t ta = (uint32_t)(lt / S.tiles_b), tb = (uint32_t)(lt - (uint64_t)ta * S.tiles_b);
+    const uint32_t a0 = ta * kScalarTA, b = tb * kScalarTB + (uint32_t)lane;
+    const uint32_t na = min((uint32_t)kScalarTA, R.nA - a0);
+    const bool b_ok = b < R.nB;
+    for (uint32_t qi = 0; qi < A.n_queries; ++qi) {
+      const QueryDev& Q = A.queries[qi];
+      if (!uni32(Q.active)) continue;
+      const uint32_t* bits = uni_ptr(Q.subset_bits);
+      if (bits && !((uni32(bits[S.t >> 5]) >> (S.t & 31)) & 1u)) continue;
+      const ScalarQuery* sq = uni_ptr(Q.sq);
+      const float* col0 = uni_ptr(sq->tab);
+      const float tau_o = unif(Q.st->tau_o);
+      const uint64_t tau_id = uni64(Q.st->tau_id);
+      const float bo = b_ok ? col0[R.rowB + b] : __builtin_nanf("");
+      // the row of A values (NaN past the reaction's edge: never passes)
+      __builtin_amdgcn_wave_barrier();
+      row[lane] = (uint32_t)lane < na ? a_value(col0, R, a0 + (uint32_t)lane) : __builtin_nanf("");
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t g = 0; g < na; g += kScanGroup) {
+        float mx = -__builtin_inff();
+#pragma unroll
+        for (int u = 0; u < kScanGroup; u += 4) {
+          const float4 a4 = *reinterpret_cast<const float4*>(row + g + u);
+          mx = fmaxf(mx, a4.x + bo);
+          mx = fmaxf(mx, a4.y + bo);
+          mx = fmaxf(mx, a4.z + bo);
+          mx = fmaxf(mx, a4.w + bo);
+        }
+        if (__ballot(mx >= tau_o) == 0) continue;
+        const uint32_t ge = min(g + kScanGroup, na);
+        for (uint32_t al = g; al < ge; ++al) {
+          const float o = canon_zero(row[al] + bo);
+          bool pass = o >= tau_o;
+          if (__ballot(pass) == 0) continue;
+          const uint32_t a = a0 + al;
+          const uint64_t id = R.id_off + (uint64_t)a * R.nB + b;
+          pass = pass && finite_obj(o) && key_passes(o, id, tau_o, tau_id);
+          if (pass) pass = scalar_feasible(sq, R, a, b);
+          wave_append(Q, pass, o, id, lane);
+        }
+      }
+    }
+  }
+}
+
+// Listed compounds (the threshold warm start's sample) scored for each query
+// with the enumeration's arithmetic and appended if they pass; ids past the
+// library's end are skipped.
+__global__ __launch_bounds__(256) void k_scan_list(const uint64_t* __restrict__ ids, uint32_t n,
+                                                   const QueryDev* __restrict__ qs, uint32_t nq,
+                                                   const ReactDev* __restrict__ react, uint32_t n_react,
+                                                   uint64_t n_total) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t q = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  if (q >= nq) return;  // uniform per workgroup
+  const QueryDev& Q = qs[q];
+  if (!Q.active) return;
+  bool pass = false;
+  float o = 0.0f;
+  uint64_t id = ~0ull;
+  if (i < n) id = ids[i];
+  if (id < n_total) {
+    const uint32_t t = find_reaction(react, n_react, id);
+    if (!Q.subset_bits || ((Q.subset_bits[t >> 5] >> (t & 31)) & 1u)) {
+      const ReactDev R = react[t];
+      const uint64_t loc = id - R.id_off;
+      const uint32_t a = (uint32_t)(loc / R.nB), b = (uint32_t)(loc - (uint64_t)a * R.nB);
+      const ScalarQuery* sq = Q.sq;
+      o = canon_zero(a_value(sq->tab, R, a) + sq->tab[R.rowB + b]);
+      pass = finite_obj(o) && key_passes(o, id, Q.st->tau_o, Q.st->tau_id) && scalar_feasible(sq, R, a, b);
+    }
+  }
+  wave_append(Q, pass, o, id, lane);
+}
+
+// FP32 heads of listed compounds: heads[e * hs + h] for h < hs (zero columns
+// past H); an id past the library's end gives a row of NaN.
+__global__ __launch_bounds__(256) void k_lin_heads(const float* __restrict__ V, uint32_t hs,
+                                                   const ReactDev* __restrict__ react, uint32_t n_react,
+                                                   uint64_t n_total, const uint64_t* __restrict__ ids, uint32_t n,
+                                                   float* __restrict__ heads) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (uint64_t)n * hs) return;
+  const uint32_t e = (uint32_t)(i / hs), h = (uint32_t)(i - (uint64_t)e * hs);
+  const uint64_t id = ids[e];
+  float x = __builtin_nanf("");
+  if (id < n_total) {
+    const uint32_t t = find_reaction(react, n_react, id);
+    const ReactDev R = react[t];
+    const uint64_t loc = id - R.id_off;
+    const uint32_t a = (uint32_t)(loc / R.nB), b = (uint32_t)(loc - (uint64_t)a * R.nB);
+    float s;
+    if (R.three) {
+      const uint32_t i0 = a / R.n1, i1 = a - i0 * R.n1;
+      s = V[(uint64_t)(R.row0 + i0) * hs + h] + V[(uint64_t)(R.row1 + i1) * hs + h];
+    } else {
+      s = V[(uint64_t)(R.row0 + a) * hs + h];
+    }
+    x = s + V[(uint64_t)(R.rowB + b) * hs + h];
+  }
+  heads[i] = x;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_qtab(const float* V, uint32_t hs, uint64_t rows, uint32_t H, const ScalarQuery* sq,
+                       hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qtab, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, V, hs, rows, H, sq);
+  return hipGetLastError();
+}
+
+hipError_t scan_prepare(int* max_wg_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(max_wg_per_cu, reinterpret_cast<const void*>(&k_scan),
+                                                      kScanWaves * 64, 0);
+}
+
+hipError_t launch_scan(const EnumArgs& a, uint32_t grid_max, hipStream_t s) {
+  const uint64_t nt = a.tile_end - a.tile_begin;
+  if (nt == 0) return hipSuccess;
+  const uint64_t want = (nt + kScanWaves - 1) / kScanWaves;
+  const uint32_t grid = (uint32_t)(want < grid_max ? want : grid_max);
+  hipLaunchKernelGGL(k_scan, dim3(grid), dim3(kScanWaves * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_list(const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq, const ReactDev* react,
+                            uint32_t n_react, uint64_t n_total, hipStream_t s) {
+  if (n == 0 || nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_list, dim3((n + 255) / 256, nq), dim3(256), 0, s, ids, n, qs, nq, react, n_react,
+                     n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_lin_heads(const float* V, uint32_t hs, const ReactDev* react, uint32_t n_react, uint64_t n_total,
+                            const uint64_t* ids, uint32_t n, float* heads, hipStream_t s) {
+  const uint64_t m = (uint64_t)n * hs;
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lin_heads, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, V, hs, react, n_react, n_total,
+                     ids, n, heads);
+  return hipGetLastError();
+}
+
+}  // namespace apex

@@ -64,7 +64,7 @@ std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint
   return out;
 }
 
-uint32_t tile_compounds(int prec) { return (uint32_t)(tile_ta(prec) * tile_tb(prec)); }
+uint32_t tile_compounds(bool scalar) { return (uint32_t)(tile_ta(scalar) * tile_tb(scalar)); }
 
 apex_status validate_query(const apex_engine* E, const apex_query* q) {
   if (!q) return set_error(APEX_E_INVALID, "null query");
@@ -100,9 +100,35 @@ apex_status validate_query(const apex_engine* E, const apex_query* q) {
   return APEX_OK;
 }
 
-void query_sizes(const apex_query* q, QPlan& P) {
+// Distinct constrained heads of a query, with their intersected bounds.
+static uint32_t constrained_heads(const apex_query* q, uint32_t* head, float* lo, float* hi) {
+  uint32_t n = 0;
+  for (uint32_t c = 0; c < q->n_constraints; ++c) {
+    const apex_constraint& k = q->constraints[c];
+    uint32_t j = 0;
+    while (j < n && head[j] != k.head) ++j;
+    if (j == n) {
+      head[n] = k.head;
+      lo[n] = -INFINITY;
+      hi[n] = INFINITY;
+      ++n;
+    }
+    lo[j] = std::max(lo[j], k.lo);
+    hi[j] = std::min(hi[j], k.hi);
+  }
+  return n;
+}
+
+void query_sizes(const apex_engine* E, const apex_query* q, QPlan& P) {
   P.k = (uint32_t)q->k;
   P.lowp = q->precision != APEX_PREC_FP32;
+  P.hs = E->HS;
+  if (E->scalar) {
+    uint32_t head[APEX_MAX_CONSTRAINTS];
+    float lo[APEX_MAX_CONSTRAINTS], hi[APEX_MAX_CONSTRAINTS];
+    P.n_cols = 1 + constrained_heads(q, head, lo, hi);
+    P.tab_rows = E->lib->rows;
+  }
   const uint32_t pf = q->pool_factor ? q->pool_factor : 4;
   P.K = P.lowp ? pf * P.k : P.k;
   uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(64ull * P.K, 1ull << 18), 1ull << 22);
@@ -124,6 +150,14 @@ void query_layout(uint32_t T, uint32_t n_flags, Bump& b, QPlan& p) {
   p.tmp_id = b.take<uint64_t>(p.K);
   p.subset_dev = b.take<uint32_t>((T + 31) / 32);
   p.sel = b.take<SelScratch>(1);
+  if (p.n_cols) {
+    p.sq = b.take<ScalarQuery>(1);
+    p.tab = b.take<float>((size_t)p.n_cols * p.tab_rows);
+  }
+  // answers longer than one workgroup's sort are radix-sorted (the FP32 answer,
+  // or the whole rescored pool of a low-precision search)
+  const uint32_t sort_n = p.lowp ? p.cap2 : p.K;
+  if (sort_n > kSortSmallMax) p.rs_hist = b.take<uint32_t>(radix_hist_words(sort_n));
   if (p.lowp) {
     p.pool_heads = b.take<float>((size_t)p.K * kHeadsPad);
     p.cand2_o = b.take<float>(p.cap2);
@@ -141,7 +175,7 @@ void out_layout(Bump& b, QPlan& p) {
   p.rerun = b.take<uint32_t>(p.n_flags);
   p.fin_o = b.take<float>(p.k);
   p.fin_id = b.take<uint64_t>(p.k);
-  p.fin_heads = b.take<float>((size_t)p.k * kHeadsPad);
+  p.fin_heads = b.take<float>((size_t)p.k * p.hs);
   p.fin_reaction = b.take<uint32_t>(p.k);
   p.fin_synthon = b.take<uint32_t>((size_t)p.k * 3);
   p.out_bytes = b.off - off0;
@@ -202,11 +236,15 @@ QueryDev make_qdev(const apex_engine* E, const apex_query* q, const QPlan& p, bo
     d.lo[h] = -INFINITY;
     d.hi[h] = INFINITY;
   }
+  // per-head bounds of the MLP kernels (at most 16 heads there; linear-probe
+  // engines read their bounds from the query's ScalarQuery instead)
   for (uint32_t c = 0; c < q->n_constraints; ++c) {
     const apex_constraint& k = q->constraints[c];
+    if (k.head >= (uint32_t)kHeadsPad) continue;
     d.lo[k.head] = std::max(d.lo[k.head], k.lo);
     d.hi[k.head] = std::min(d.hi[k.head], k.hi);
   }
+  d.sq = p.sq;
   if (relaxed && p.lowp) {
     const float* dl = E->prec[q->precision].delta;
     for (int h = 0; h < kHeadsPad; ++h) {
@@ -255,12 +293,23 @@ apex_status query_device_init(const apex_engine* E, const apex_query* q, const Q
   const std::vector<uint32_t> bits = subset_bits(E, q);
   if (!bits.empty())
     HIP_TRY(hipMemcpyAsync(P.subset_dev, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, s));
+  if (P.sq) {
+    // linear-probe engine: the query's per-row tables (Section 4.3: each
+    // synthon's contribution to the objective, dotted once per query)
+    ScalarQuery sq{};
+    for (uint32_t h = 0; h < E->H; ++h) sq.w[h] = q->objective_w[h];
+    sq.n_ch = constrained_heads(q, sq.head, sq.lo, sq.hi);
+    sq.tab = P.tab;
+    sq.rows = P.tab_rows;
+    HIP_TRY(hipMemcpyAsync(P.sq, &sq, sizeof(sq), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_qtab(E->P, E->HS, P.tab_rows, E->H, P.sq, s));
+  }
   return fill_u32(P.rerun, P.n_flags, 0u, s);
 }
 
 uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev>& plan, uint64_t v0, uint64_t v1) {
   uint64_t c = 0;
-  const uint64_t TA = tile_ta(prec), TB = tile_tb(prec);
+  const uint64_t TA = tile_ta(E->scalar), TB = tile_tb(E->scalar);
   for (size_t r = 0; r < plan.size(); ++r) {
     const ReactDev& rd = E->react_host[plan[r].t];
     const uint64_t ta = (rd.nA + TA - 1) / TA;
@@ -314,7 +363,10 @@ apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t
     }
     HIP_TRY(hipEventRecord(e0, s));
   }
-  HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, false, a, grid, s));
+  if (E->scalar)
+    HIP_TRY(launch_scan(a, (uint32_t)std::max(1, E->n_cu * PS.wg_per_cu), s));
+  else
+    HIP_TRY(launch_enum(prec, E->H1, E->NL, E->act, false, a, grid, s));
   if (E->profile) {
     HIP_TRY(hipEventRecord(e1, s));
     E->ev_pending.push_back({e0, e1, compounds});
@@ -338,12 +390,18 @@ apex_status profile_collect(apex_engine* E) {
 }
 
 apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_tiles,
-                       uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev, uint32_t nq,
-                       hipStream_t s) {
-  HIP_TRY(launch_sample_tiles(plan_dev, n_sel, E->react, n_tiles, n_sample, 0xa5e7c0de1234ull, ids, s));
-  apex_status st = engine_gather(E, prec, ids, n_sample, heads, s);
-  if (st != APEX_OK) return st;
-  HIP_TRY(launch_score(heads, ids, n_sample, nullptr, qd_dev, nq, E->react, E->lib->T, s));
+                       uint64_t n_comp, uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev,
+                       uint32_t nq, hipStream_t s) {
+  if (E->scalar) {
+    // distinct sampled compounds scored with the enumeration's own arithmetic
+    HIP_TRY(launch_sample_ids(plan_dev, n_sel, E->react, n_comp, n_sample, 0xa5e7c0de1234ull, ids, s));
+    HIP_TRY(launch_scan_list(ids, n_sample, qd_dev, nq, E->react, E->lib->T, E->lib->total, s));
+  } else {
+    HIP_TRY(launch_sample_tiles(plan_dev, n_sel, E->react, n_tiles, n_sample, 0xa5e7c0de1234ull, ids, s));
+    apex_status st = engine_gather(E, prec, ids, n_sample, heads, s);
+    if (st != APEX_OK) return st;
+    HIP_TRY(launch_score(heads, ids, n_sample, nullptr, qd_dev, nq, E->react, E->lib->T, s));
+  }
   HIP_TRY(launch_select(qd_dev, nq, 0, 1, s));
   HIP_TRY(launch_tau_relax(qd_dev, nq, s));
   return APEX_OK;
@@ -355,10 +413,26 @@ static uint32_t* rank_scratch(const QPlan& P) {
   return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(P.sel) + offsetof(SelScratch, br_key));
 }
 
+// Bytes of the largest compound id (the id digits of the radix sort).
+static uint32_t id_bytes(const apex_engine* E) {
+  uint64_t m = E->lib->total ? E->lib->total - 1 : 0;
+  uint32_t n = 1;
+  while (m >>= 8) ++n;
+  return n;
+}
+
 apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev, const QueryDev* qx_dev,
                           hipStream_t s) {
   if (!P.lowp) {
-    HIP_TRY(launch_rank_sort(qd_dev, 0, P.K, P.fin_o, P.fin_id, rank_scratch(P), s));
+    if (P.K > kSortSmallMax) {
+      // scratch: the compaction buffer and the candidate buffer past its first
+      // K entries (the K survivors stay intact for a re-run after an overflow)
+      HIP_TRY(launch_radix_sort(P.st, P.K, P.cand_o, P.cand_id, reinterpret_cast<uint32_t*>(P.tmp_o), P.tmp_id,
+                                reinterpret_cast<uint32_t*>(P.cand_o + P.K), P.cand_id + P.K, P.fin_o, P.fin_id, P.k,
+                                id_bytes(E), P.rs_hist, s));
+    } else {
+      HIP_TRY(launch_rank_sort(qd_dev, 0, P.K, P.fin_o, P.fin_id, rank_scratch(P), s));
+    }
     // rows past the answer's length are computed from stale ids and never read
     apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, P.k, P.fin_heads, s);
     if (st != APEX_OK) return st;
@@ -372,8 +446,10 @@ apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev
       // the rescored pool fits one workgroup: sort all of it, keep the first k
       HIP_TRY(launch_sort_small(qx_dev, 0, P.cap2, P.k, P.fin_o, P.fin_id, rank_scratch(P), s));
     } else {
-      HIP_TRY(launch_select(qx_dev, 1, 0, 1, s));
-      HIP_TRY(launch_rank_sort(qx_dev, 0, P.k, P.fin_o, P.fin_id, rank_scratch(P), s));
+      // the whole rescored pool, radix-sorted; the first k are the answer
+      HIP_TRY(launch_radix_sort(P.st2, P.cap2, P.cand2_o, P.cand2_id, reinterpret_cast<uint32_t*>(P.tmp_o),
+                                P.tmp_id, reinterpret_cast<uint32_t*>(P.cand_o + P.K), P.cand_id + P.K, P.fin_o,
+                                P.fin_id, P.k, id_bytes(E), P.rs_hist, s));
     }
     // the answer is part of the rescored pool
     HIP_TRY(launch_pool_lookup(P.cand_id, P.pool_heads, P.K, P.st, P.fin_id, P.k, P.st2, P.fin_heads, s));
@@ -406,7 +482,7 @@ void finish_read(const apex_engine* E, const QPlan& P, const char* host, const c
   if (res->heads) {
     const float* h = in_copy(host, base, P.fin_heads);
     for (uint32_t e = 0; e < n_found; ++e)
-      std::memcpy(res->heads + (size_t)e * E->H, h + (size_t)e * kHeadsPad, sizeof(float) * E->H);
+      std::memcpy(res->heads + (size_t)e * E->H, h + (size_t)e * P.hs, sizeof(float) * E->H);
   }
   if (res->reaction) std::memcpy(res->reaction, in_copy(host, base, P.fin_reaction), sizeof(uint32_t) * n_found);
   if (res->synthon) std::memcpy(res->synthon, in_copy(host, base, P.fin_synthon), sizeof(uint32_t) * 3 * n_found);
@@ -439,9 +515,9 @@ uint32_t sample_count(const std::vector<QPlan>& P) {
 void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& b, std::vector<QPlan>& P,
                   Shared& sh) {
   P.assign(n, QPlan());
-  for (uint32_t i = 0; i < n; ++i) query_sizes(&qs[i], P[i]);
+  for (uint32_t i = 0; i < n; ++i) query_sizes(E, &qs[i], P[i]);
   const int prec = (int)qs[0].precision;
-  sh.n_flags = (uint32_t)chunk_schedule(E->prec[prec].full_tiles, tile_compounds(prec)).size() + 1;
+  sh.n_flags = (uint32_t)chunk_schedule(E->prec[prec].full_tiles, tile_compounds(E->scalar)).size() + 1;
   sh.n_sample = sample_count(P);
   const uint32_t T = E->lib->T;
   sh.qd = b.take<QueryDev>(n);
@@ -494,7 +570,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
     if (want[t]) reactions.push_back(t);
   std::vector<SelDev> plan;
   uint64_t n_tiles = 0, n_comp = 0;
-  build_plan(L, prec, reactions, plan, &n_tiles, &n_comp);
+  build_plan(L, E->scalar, reactions, plan, &n_tiles, &n_comp);
 
   std::vector<QueryDev> qd(nq), qx(nq);
   for (uint32_t i = 0; i < nq; ++i) {
@@ -511,14 +587,14 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   uint64_t scored = 0;
   // 1. threshold warm start from a stratified sample of the searched reactions
   if (n_comp >= 8ull * sh.n_sample) {
-    apex_status st = warm_start(E, prec, sh.plan, (uint32_t)plan.size(), n_tiles, sh.n_sample, sh.sample_ids,
-                                sh.sample_heads, sh.qd, nq, s);
+    apex_status st = warm_start(E, prec, sh.plan, (uint32_t)plan.size(), n_tiles, n_comp, sh.n_sample,
+                                sh.sample_ids, sh.sample_heads, sh.qd, nq, s);
     if (st != APEX_OK) return st;
     scored += sh.n_sample;
   }
 
   // 2. chunked enumeration
-  const auto chunks = chunk_schedule(n_tiles, tile_compounds(prec));
+  const auto chunks = chunk_schedule(n_tiles, tile_compounds(E->scalar));
   if (chunks.size() + 1 > sh.n_flags) return set_error(APEX_E_INVALID, "internal: chunk count");
   const uint32_t last_flag = sh.n_flags - 1;  // flag slot of the closing selections (never set)
   for (size_t c = 0; c < chunks.size(); ++c) {

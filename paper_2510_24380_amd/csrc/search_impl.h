@@ -26,6 +26,12 @@ struct Bump {
 struct QPlan {
   uint32_t k = 0, K = 0, cap = 0, hwm = 0, cap2 = 0, n_flags = 0;
   bool lowp = false;
+  uint32_t hs = kHeadsPad;        // row stride of the answer's heads
+  uint32_t n_cols = 0;            // linear-probe engines: per-row table columns (0 otherwise)
+  uint64_t tab_rows = 0;
+  ScalarQuery* sq = nullptr;      // linear-probe engines: the query's tables
+  float* tab = nullptr;
+  uint32_t* rs_hist = nullptr;    // radix-sort scratch (answers above kSortSmallMax entries)
   char* out = nullptr;
   size_t out_bytes = 0;
   QState* st = nullptr;
@@ -51,9 +57,9 @@ struct QPlan {
 
 uint64_t env_u64(const char* name);
 std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint64_t tile_compounds);
-uint32_t tile_compounds(int prec);
+uint32_t tile_compounds(bool scalar);
 apex_status validate_query(const apex_engine* E, const apex_query* q);
-void query_sizes(const apex_query* q, QPlan& P);
+void query_sizes(const apex_engine* E, const apex_query* q, QPlan& P);
 // Per-query working buffers from a bump allocator (sets n_flags); then
 // out_layout takes the query's readback block.
 void query_layout(uint32_t n_reactions, uint32_t n_flags, Bump& b, QPlan& P);
@@ -68,11 +74,11 @@ apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t
                       const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, hipStream_t s);
 // Compounds of a host tile plan inside tiles [v0, v1).
 uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev>& plan, uint64_t v0, uint64_t v1);
-// Threshold warm start from a sample of compounds of a tile plan (n_tiles tiles)
-// for the listed queries (async).
+// Threshold warm start from a sample of compounds of a tile plan (n_tiles tiles,
+// n_comp compounds) for the listed queries (async).
 apex_status warm_start(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t n_tiles,
-                       uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev, uint32_t nq,
-                       hipStream_t s);
+                       uint64_t n_comp, uint32_t n_sample, uint64_t* ids, float* heads, const QueryDev* qd_dev,
+                       uint32_t nq, hipStream_t s);
 // Stage 3-4 device work of a query whose enumeration has been enqueued (async):
 // FP32 rescoring of a low-precision pool, the ordered answer, its heads and
 // decoding, all into the readback block. Every count it needs is read on the

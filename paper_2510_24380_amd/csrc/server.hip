@@ -150,7 +150,7 @@ struct apex_server {
 namespace {
 
 size_t query_bytes(const apex_server* S, const apex_query* q, QPlan* P) {
-  query_sizes(q, *P);
+  query_sizes(S->E, q, *P);
   Bump b(nullptr);
   query_layout(S->E->lib->T, (uint32_t)S->chunks.size() + 1, b, *P);
   out_layout(b, *P);
@@ -171,7 +171,7 @@ void chunk_plan(apex_server* S, int prec, const Chunk& ch, const std::vector<SQ*
     }
     if (want) rs.push_back(t);
   }
-  build_plan(S->E->lib, prec, rs, plan, n_tiles, n_comp);
+  build_plan(S->E->lib, S->E->scalar, rs, plan, n_tiles, n_comp);
 }
 
 bool chunk_wanted(const Chunk& ch, const SQ* q) {
@@ -243,8 +243,8 @@ apex_status admit(apex_server* S, SQ* q) {
   if (E->lib->total >= 8ull * n_sample && q->n_comp >= 8ull * n_sample) {
     st = upload_active(S, {q->slot});
     if (st != APEX_OK) return st;
-    st = warm_start(E, prec, E->prec[prec].plan, E->lib->T, E->prec[prec].full_tiles, n_sample, S->sample_ids,
-                    S->sample_heads, S->qd_dev, (uint32_t)S->qd.size(), S->s);
+    st = warm_start(E, prec, E->prec[prec].plan, E->lib->T, E->prec[prec].full_tiles, E->prec[prec].full_compounds,
+                    n_sample, S->sample_ids, S->sample_heads, S->qd_dev, (uint32_t)S->qd.size(), S->s);
     if (st != APEX_OK) return st;
     q->n_scored += n_sample;
   }
@@ -497,7 +497,8 @@ extern "C" apex_status apex_server_create(apex_engine* eng, const apex_server_co
     if (n_t > target) {
       if (acc > 0) S->chunks.push_back({r0, t, acc});
       const ReactDev& rd = eng->react_host[t];
-      const uint64_t tiles = (uint64_t)((rd.nA + tile_ta(0) - 1) / tile_ta(0)) * ((rd.nB + tile_tb(0) - 1) / tile_tb(0));
+      const uint64_t TA = tile_ta(eng->scalar), TB = tile_tb(eng->scalar);
+      const uint64_t tiles = ((rd.nA + TA - 1) / TA) * ((rd.nB + TB - 1) / TB);
       const uint64_t pieces = (n_t + target - 1) / target;
       const uint64_t per = (tiles + pieces - 1) / pieces;
       for (uint64_t v = 0; v < tiles; v += per)

@@ -93,5 +93,7 @@ def test_decoder_validation():
     assert create([64, 128, 64, 5]) == 0
     assert create([64, 128, 40, 5]) == -4     # second hidden width not a multiple of 32
     assert create([64, 0, 5]) == -1
-    assert create([64, 28]) == -4            # linear probe wider than one MFMA tile
+    assert create([64, 28]) == 0             # the paper's 28-head linear probe
+    assert create([64, 32]) == 0
+    assert create([64, 33]) == -4            # more than 32 linear heads
     assert create([64, 5]) == 0              # linear probe (one layer)

@@ -1,0 +1,76 @@
+"""Long answers, as in the paper's runtime table (Table tab:runtime: k = 1e4,
+1e5 and 1e6), against the FP64 oracle through the C ABI: the candidate buffers
+grow with k, the answer and the low-precision pool are radix-sorted.
+
+- the linear probe (28 heads, d = 64) on a 12-million-compound library of the
+  benchmark recipe, with the runtime table's query (a docking head minimised
+  under four upper bounds), k = 1e5 and 1e6 in FP32: exact id sets;
+- a two-layer decoder (64 -> 128 -> 5, ReLU) on 1.2 million compounds, k = 1e5 in
+  FP32 (exact id set) and BF16 (recall against the oracle over a 4e5 pool)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads.gen as g
+from workloads.gen import ACT_RELU, Constraint, Query
+
+pytestmark = pytest.mark.gpu
+
+from parity import check_fp32_exact, check_lowp
+
+if torch.cuda.is_available():
+    from gpu_helpers import device_objects
+
+
+@pytest.fixture(scope="module")
+def probe12m():
+    n_slots, sizes = g.library_shapes_probe(11, 12_000_000)
+    lib_h, dec_h = g.config_probe(11, n_slots, sizes)
+    sample = oracle.heads(lib_h, dec_h, g.sample_ids(11, "probe_sample", lib_h.n_compounds, 1 << 14))
+    objs = device_objects(lib_h, dec_h, precisions=("fp32",))
+    return lib_h, dec_h, objs, sample
+
+
+@pytest.mark.parametrize("k", [100_000, 1_000_000])
+def test_probe_12m_long_answers(probe12m, k):
+    lib_h, dec_h, (lib, dec, eng), sample = probe12m
+    q = g.probe_query(12, lambda h, p: float(np.quantile(sample[:, h], p)), k, target=3)
+    print(f"case: probe 12M ({lib_h.n_compounds} compounds) k={k}", flush=True)
+    r = eng.search(q)
+    assert r.n_scored >= lib_h.n_compounds
+    check_fp32_exact(lib_h, dec_h, q, r, f"probe 12M k={k}")
+
+
+@pytest.fixture(scope="module")
+def mlp1m():
+    lib_h = g.make_library(13, [2, 3, 2], [900, 800, 30, 40, 50, 310, 1000], 64)
+    dec_h = g.make_decoder(13, [64, 128, 5], ACT_RELU)
+    sample = oracle.heads(lib_h, dec_h, g.sample_ids(13, "mlp_sample", lib_h.n_compounds, 1 << 13))
+    objs = device_objects(lib_h, dec_h, precisions=("fp32", "bf16"))
+    return lib_h, dec_h, objs, sample
+
+
+def _mlp_query(sample, k):
+    w = np.array([1.0, 0.0, -0.5, 0.25, 0.0], np.float32)
+    cons = [Constraint(1, -math.inf, float(np.float32(np.quantile(sample[:, 1], 0.7)))),
+            Constraint(4, float(np.float32(np.quantile(sample[:, 4], 0.2))), math.inf)]
+    return Query(w=w, constraints=cons, k=k)
+
+
+def test_mlp_long_answer_fp32(mlp1m):
+    lib_h, dec_h, (lib, dec, eng), sample = mlp1m
+    q = _mlp_query(sample, 100_000)
+    print(f"case: mlp {lib_h.n_compounds} compounds fp32 k=1e5", flush=True)
+    r = eng.search(q, precision="fp32")
+    check_fp32_exact(lib_h, dec_h, q, r, "mlp fp32 k=1e5")
+
+
+def test_mlp_long_answer_bf16(mlp1m):
+    lib_h, dec_h, (lib, dec, eng), sample = mlp1m
+    q = _mlp_query(sample, 100_000)
+    print(f"case: mlp {lib_h.n_compounds} compounds bf16 k=1e5 (pool 4e5)", flush=True)
+    r = eng.search(q, precision="bf16")
+    check_lowp(lib_h, dec_h, q, r, "mlp bf16 k=1e5")

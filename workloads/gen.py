@@ -341,6 +341,51 @@ def library_shapes_c1(seed: int = 1):
     return n_slots, flat
 
 
+def library_shapes_probe(seed: int, target: int, T: int = 40, n3: int = 12):
+    """The benchmark library recipe (T reactions, n3 of them three-slot, per-slot
+    counts lognormal with median 150 in [20, 3000]) capped to about `target`
+    compounds."""
+    order = np.argsort(uniform_f64(seed, "three_slot_pick", T), kind="stable")
+    three = set(int(i) for i in order[:n3])
+    n_slots = [3 if t in three else 2 for t in range(T)]
+    raw = lognormal_counts(seed, "slot_counts", sum(n_slots), 150.0, 1.0, 20, 3000)
+    sizes, p = [], 0
+    for t in range(T):
+        sizes.append([int(x) for x in raw[p:p + n_slots[t]]])
+        p += n_slots[t]
+    _cap_total(n_slots, sizes, target, 20)
+    return n_slots, [x for s in sizes for x in s]
+
+
+def config_probe(seed: int, n_slots, sizes, d: int = 64, n_heads: int = 28):
+    """A library of the given shape with the paper's surrogate head: embedding
+    width d = 64 and a LinearProbe of 28 linear heads (Section 5.1 and Appendix
+    A.8), Xavier weights from the seed."""
+    lib = make_library(seed, n_slots, sizes, d)
+    dec = make_decoder(seed, [d, n_heads], ACT_NONE)
+    return lib, dec
+
+
+def probe_query(seed: int, head_quantile, k: int, target: int = 0, n_heads: int = 28, lipinski: bool = True):
+    """The runtime table's query (Section 5.2, Table tab:runtime): minimise the
+    docking score of one target (heads 0..4 stand for the five targets; w = -1)
+    under the four Lipinski bounds (Appendix A.7, Table tab:constraints: four
+    upper bounds), here on four seeded property heads (5..n_heads-1), each at a
+    seeded quantile in [0.6, 0.9] of the head's distribution
+    (`head_quantile(head, q)`)."""
+    w = np.zeros(n_heads, dtype=np.float32)
+    w[target] = -1.0
+    cons = []
+    if lipinski:
+        props = list(range(5, n_heads))
+        perm = np.argsort(uniform_f64(seed, "probe_heads", len(props)), kind="stable")
+        quant = 0.6 + 0.3 * uniform_f64(seed, "probe_quant", 4)
+        for i in range(4):
+            h = props[int(perm[i])]
+            cons.append(Constraint(h, -math.inf, float(np.float32(head_quantile(h, float(quant[i]))))))
+    return Query(w=w, constraints=cons, k=k)
+
+
 def config_c0():
     """Tiny FP32 case: 1 reaction, 2 slots x 300 synthons, d=64, MLP 64->128 (ReLU)->5;
     maximise head 0 with head1 <= 0.5 and head2 >= -0.5, k = 100."""
