@@ -10,7 +10,16 @@ sorted and decoded. Inputs (tables, weights) are resident in HBM before timing.
 
 Prints one JSON line. `value` is the headline precision's compounds/s; the other
 precisions, recall@k against the FP64 oracle's stored answer, the roofline of
-the fused kernel and the CPU oracle's rate are reported beside it.
+the fused kernel and the CPU oracle's rate are reported beside it. The default
+run adds the other measured workloads as legs of the same line:
+  - "c3": the 2.9e10-compound library streamed, one search each in BF16 and FP8;
+  - "serving_c4": a Poisson query stream over reaction subsets of that library
+    (1e6 to 1e9 compounds each), shortened to what one GPU serves;
+  - "probe_runtime_table": the paper's own configuration (a 28-head linear
+    probe, d = 64) on libraries shaped like its 12M, 10B and 70B ones, at the
+    k values and constraint sets of its runtime table, beside its T4 times;
+  - "cpu_baseline": the FP64 oracle on the host (CPU model, threads, a
+    single-thread rate, the tiny case in full).
 """
 import argparse
 import json
@@ -27,6 +36,22 @@ sys.path.insert(0, ROOT)
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}  # dense MFMA, MI355X
 METRIC = "compounds/s scored+top-k, BF16/FP8 vs FP32 @ recall@k>=0.99; p99 query latency"
+# vector ALU: 256 CUs x 64 lanes x 2.4 GHz (one FP32 operation per lane and clock, unpacked)
+VALU_PEAK = 256 * 64 * 2.4e9
+
+# The paper's runtime table (Table tab:runtime): end-to-end seconds on one NVIDIA
+# Tesla T4 with its linear probe, averaged over five docking targets; the
+# parenthesised CPU times of the table are "cpu".
+PAPER_T4 = {
+    "hardware": "one NVIDIA Tesla T4 (CPU model not stated); times include building an output table with "
+                "SMILES, which this engine does not do",
+    "none": {"12M": {10**4: (0.3, 0.4), 10**5: (1.2, 1.2), 10**6: (10.9, 12.7)},
+             "10B": {10**4: (10.9, 130.7), 10**5: (11.6, 131.4), 10**6: (21.2, 147.6)},
+             "70B": {10**4: (168.4, 838.5), 10**5: (169.3, 847.2), 10**6: (184.0, 858.9)}},
+    "lipinski": {"12M": {10**4: (0.3, 0.7), 10**5: (0.9, 1.7), 10**6: (10.8, 12.9)},
+                 "10B": {10**4: (13.9, 437.7), 10**5: (14.6, 443.7), 10**6: (24.3, 462.2)},
+                 "70B": {10**4: (186.1, 3163.2), 10**5: (187.5, 3184.6), 10**6: (202.4, 3142.5)}},
+}
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = "paper_2510_24380_amd/csrc/"
 
@@ -317,6 +342,172 @@ def main_c3(args):
     print(json.dumps(out), flush=True)
 
 
+def c3_leg(precisions=("bf16", "fp8"), serve_queries=60, serve_qps=2.0, seq_queries=3):
+    """The 2.9e10-compound library: one search per precision (the kernels are
+    already loaded by the headline run), then a shortened serving stream over its
+    reaction subsets. Returns (c3, serving) dicts; the engine is freed after."""
+    import torch
+    from workloads.gen import Constraint, Query
+    t0 = time.perf_counter()
+    lib_h, dec_h, counts, lib, eng = build_c3(("fp32",) + tuple(precisions))
+    spec = json.load(open(os.path.join(GOLDEN, "c3_query.json")))["query"]
+    cons = [Constraint(c["head"], -math.inf if c["lo"] is None else c["lo"],
+                       math.inf if c["hi"] is None else c["hi"]) for c in spec["constraints"]]
+    q = Query(w=np.array(spec["w"], np.float32), constraints=cons, k=spec["k"])
+    n = lib.num_compounds
+    setup_s = time.perf_counter() - t0
+    log(f"c3: engine ready ({n} compounds, {setup_s:.0f} s)")
+    flops_c = algorithmic_flops_per_compound(dec_h.dims)
+    c3 = {"workload": "2.9e10-compound synthetic CSL streamed (2000 reactions, lognormal slot sizes median 800 up "
+                      "to 10000), d=256, decoder 256->512->512 (SiLU)->15, objective = weighted sum of 3 heads, "
+                      "6 one-sided bounds, k=10000, 4k pool rescored in FP32; one search per precision",
+          "n_compounds": n, "setup_s": setup_s}
+    top = {}
+    for prec in precisions:
+        eng.profile(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = eng.search(q, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ms, launches, comps = eng.profile(False)
+        achieved = flops_c * comps / (ms * 1e-3) if ms > 0 else 0.0
+        top[prec] = [int(x) for x in r.ids[:100]]
+        c3[prec] = {"seconds": dt, "compounds_per_s": n / dt, "n_found": len(r.ids), "candidates": r.n_candidates,
+                    "reruns": r.n_reruns,
+                    "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
+                                 "unit": "TFLOP/s", "frac": achieved / PEAK[prec],
+                                 "traffic": measured_traffic(prec, "c3"), "traffic_unit": "bytes/launch",
+                                 "kernel": f"apex::{fused_kernel(prec)[0]} (fused)",
+                                 "avg_launch_ms": ms / max(launches, 1), "launches": launches}}
+        log(f"c3 {prec}: {n / dt:.4g} compounds/s ({dt:.1f} s)")
+    if len(top) == 2:
+        a, b = list(top.values())
+        c3["top100_overlap_between_precisions"] = len(set(a) & set(b)) / max(1, len(a))
+    serving = None
+    if serve_queries:
+        H = np.array(json.load(open(os.path.join(GOLDEN, "c3_heads_sample.json")))["heads"])
+        serving = serve_bench(eng, counts, H, serve_queries, serve_qps, 1e6, 1e9, prec=precisions[0],
+                              chunk_compounds=1 << 26, seed=5, n_seq=seq_queries, capacity=False)
+        serving["stream"] = (f"{serve_queries} queries, Poisson {serve_qps}/s, reaction subsets of the "
+                             "2.9e10-compound library with 1e6-1e9 compounds each, random objectives over 15 heads, "
+                             "2-6 bounds, k in {100, 1000, 10000}; shortened from 2,000 queries at 5/s, which offer "
+                             "about 3e9 compounds/s, more than one GPU evaluates")
+        log("c4 serving stream done")
+    del eng, lib
+    torch.cuda.empty_cache()
+    return c3, serving
+
+
+def probe_leg(targets=5):
+    """The paper's own configuration: a 28-head linear probe on d = 64 embeddings,
+    libraries shaped like its BRICS 12M, BRICS 10B and Enamine REAL 70B ones, the
+    runtime table's k values with no constraints and with the four Lipinski
+    bounds, each time averaged over five docking-head objectives. Seconds are
+    end to end through the C ABI (query tables, enumeration, selection, answer
+    sort, heads, decode, readback into host arrays)."""
+    import torch
+    import paper_2510_24380_amd as apex
+    import workloads.gen as gen
+    shapes = [("12M", 11, lambda: gen.library_shapes_probe(11, 12_450_000)),
+              ("10B", 21, lambda: gen.config_c3_shape(21, 1e10)),
+              ("70B", 22, lambda: gen.config_c3_shape(22, 7e10))]
+    out = {"decoder": "linear probe, 28 heads, d=64 (Section 5.1, Appendix A.8)",
+           "query": "minimise one docking head (heads 0-4, one per run) with no bounds or with four one-sided "
+                    "Lipinski-style bounds on seeded property heads at seeded quantiles in [0.6, 0.9]",
+           "paper_t4": PAPER_T4["hardware"], "libraries": []}
+    for name, seed, shape in shapes:
+        t0 = time.perf_counter()
+        n_slots, sizes = shape()
+        lib_h, dec_h = gen.config_probe(seed, n_slots, sizes)
+        tables = torch.from_numpy(lib_h.tables).cuda()
+        del lib_h.tables
+        lib = apex.Library(lib_h.n_slots, lib_h.slot_sizes, tables)
+        dec = apex.Decoder(dec_h.dims, "none", [torch.from_numpy(w).cuda() for w in dec_h.W],
+                           [torch.from_numpy(b).cuda() for b in dec_h.b])
+        eng = apex.Engine(lib, dec, precisions=("fp32",))
+        n = lib.num_compounds
+        # bounds at quantiles of the engine's own FP32 heads of seeded compounds
+        hs = eng.heads(gen.sample_ids(seed, "probe_sample", n, 1 << 14))
+        quant = lambda h, p: float(np.quantile(hs[:, h], p))  # noqa: E731
+        entry = {"library": f"{name}-shaped synthetic", "n_compounds": n, "rows": int(sum(sizes)),
+                 "setup_s": time.perf_counter() - t0, "runs": []}
+        eng.search(gen.probe_query(seed + 1, quant, 10**4, target=0))
+        for cons in ("none", "lipinski"):
+            for k in (10**4, 10**5, 10**6):
+                qs = [gen.probe_query(seed + 1, quant, k, target=t, lipinski=cons == "lipinski")
+                      for t in range(targets)]
+                eng.profile(True)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                found = [len(eng.search(q).ids) for q in qs]
+                dt = (time.perf_counter() - t1) / len(qs)
+                ms, launches, comps = eng.profile(False)
+                kr = comps / (ms * 1e-3) if ms > 0 else 0.0
+                t4, cpu = PAPER_T4[cons][name][k]
+                entry["runs"].append({
+                    "constraints": cons, "k": k, "seconds": dt, "compounds_per_s": n / dt,
+                    "kernel_ms": ms / len(qs), "kernel_compounds_per_s": kr, "n_found_min": min(found),
+                    "roofline": {"bound": "alu", "achieved": 2 * kr / 1e12, "peak": VALU_PEAK / 1e12,
+                                 "unit": "Tops/s", "frac": 2 * kr / VALU_PEAK,
+                                 "ops_per_compound": "2 (objective add, threshold compare)",
+                                 "kernel": "apex::k_scan"},
+                    "paper_t4_seconds": t4, "paper_cpu_seconds": cpu, "speedup_vs_paper_t4": t4 / dt})
+                log(f"probe {name} {cons} k={k}: {dt * 1e3:.1f} ms per search ({n / dt:.3g} compounds/s, "
+                    f"paper T4 {t4} s)")
+        out["libraries"].append(entry)
+        del eng, lib, dec, tables
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline_full(lib_h, dec_h, q):
+    """The FP64 oracle (as it is) on the host: the benchmark library and query on
+    a bounded subset (all threads), the same on a small subset with one thread,
+    the tiny case in full, and the probe configuration's 12M-shaped library in
+    full (its runtime-table query, k = 1e4, with the Lipinski bounds)."""
+    import oracle
+    import workloads.gen as gen
+    base = cpu_baseline(lib_h, dec_h, q)
+    base.update(cpu_info())
+    counts = lib_h.reaction_counts()
+    small = [min(range(len(counts)), key=lambda t: counts[t])]
+    qs = type(q)(w=q.w, constraints=q.constraints, k=q.k, reactions=small)
+    t0 = time.perf_counter()
+    oracle.topk(lib_h, dec_h, qs, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    base["single_thread"] = {"value": counts[small[0]] / dt1, "unit": "compounds/s",
+                             "sample": f"reaction {small[0]} ({counts[small[0]]} compounds), {dt1:.1f} s"}
+    base["benchmark_library_full_extrapolated_s"] = sum(counts) / base["value"]
+    c0_lib, c0_dec, c0_q = gen.config_c0()
+    t0 = time.perf_counter()
+    oracle.topk(c0_lib, c0_dec, c0_q)
+    base["tiny_case_full"] = {"seconds": time.perf_counter() - t0, "compounds": c0_lib.n_compounds}
+    n_slots, sizes = gen.library_shapes_probe(11, 12_450_000)
+    p_lib, p_dec = gen.config_probe(11, n_slots, sizes)
+    hs = oracle.heads(p_lib, p_dec, gen.sample_ids(11, "probe_sample", p_lib.n_compounds, 1 << 14))
+    pq = gen.probe_query(12, lambda h, p: float(np.quantile(hs[:, h], p)), 10**4, target=0)
+    t0 = time.perf_counter()
+    oracle.topk(p_lib, p_dec, pq)
+    dtp = time.perf_counter() - t0
+    base["probe_12M_full"] = {"seconds": dtp, "compounds_per_s": p_lib.n_compounds / dtp,
+                              "compounds": p_lib.n_compounds,
+                              "query": "linear probe, Lipinski-style bounds, k=1e4 (paper CPU: 0.7 s)"}
+    return base
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,7 +526,12 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=None, help="arrival rate (default 100/s, c4: 5/s)")
     ap.add_argument("--seq-queries", type=int, default=None,
                     help="arrivals timed one at a time in FP32 for comparison (default all, c4: 20)")
+    ap.add_argument("--legs", default="c3,c4,probe,cpu",
+                    help="legs added to the default c1 run: c3, c4 (needs c3), probe, cpu; '' for none")
     args = ap.parse_args()
+    legs = set(x for x in args.legs.split(",") if x) if not args.quick else set()
+    if args.no_cpu_baseline:
+        legs.discard("cpu")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the search runs on a single MI355X (a multi-GPU run would split "
               "the reaction list into contiguous compound ranges, one per GPU, and merge the per-GPU top-k)",
@@ -458,11 +654,24 @@ def main():
         H = np.array(json.load(open(os.path.join(GOLDEN, "c1_heads_sample.json")))["heads"])
         out["serving"] = serve_bench(eng, lib_h.reaction_counts(), H, args.serve_queries, args.serve_qps, 1e5, 1e7,
                                      n_seq=args.seq_queries)
+        out["serving"]["stream"] = (f"{args.serve_queries} queries, Poisson {args.serve_qps}/s, reaction subsets "
+                                    "of the 1.04e7-compound library with 1e5-1e7 compounds each")
         log("serving stream done")
-        out["p99_latency_ms"] = out["serving"]["served"]["p99_latency_ms"]
-    if not args.no_cpu_baseline and not args.quick:
+        out["p99_latency_ms_c1_stream"] = out["serving"]["served"]["p99_latency_ms"]
+    del eng
+    torch.cuda.empty_cache()
+    if "c3" in legs:
+        c3, c4 = c3_leg(serve_queries=60 if "c4" in legs else 0)
+        out["c3"] = c3
+        if c4 is not None:
+            out["serving_c4"] = c4
+            out["p99_latency_ms"] = c4["served"]["p99_latency_ms"]
+            out["p99_latency_stream"] = c4["stream"]
+    if "probe" in legs:
+        out["probe_runtime_table"] = probe_leg()
+    if "cpu" in legs:
         log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(lib_h, dec_h, q)
+        out["cpu_baseline"] = cpu_baseline_full(lib_h, dec_h, q)
     print(json.dumps(out), flush=True)
 
 

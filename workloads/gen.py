@@ -410,11 +410,11 @@ def config_c1(seed: int = 1):
     return config_c1_model(seed)
 
 
-def config_c3_shape(seed: int = 2):
+def config_c3_shape(seed: int = 2, target: float = 3e10):
     """2,000 reactions with 2 or 3 slots, per-slot counts lognormal (median 800,
     at most 10,000). The number of three-slot reactions is the smallest that
-    reaches 3e10 compounds; the largest reactions are then trimmed to at most
-    3e10. Returns (n_slots, sizes)."""
+    reaches `target` compounds (3e10 for the large case); the largest reactions
+    are then trimmed to at most the target. Returns (n_slots, sizes)."""
     T = 2000
     raw = lognormal_counts(seed, "slot_counts", 3 * T, 800.0, 1.0, 20, 10_000)
     pick = uniform_f64(seed, "three_slot_pick", T)
@@ -426,7 +426,7 @@ def config_c3_shape(seed: int = 2):
         for t in range(T):
             a, b, c = (int(x) for x in raw[3 * t:3 * t + 3])
             total += a * b * c if t in three else a * b
-        if total >= 3e10:
+        if total >= target:
             n3 = m
             break
     three = set(int(i) for i in order[:n3])
@@ -435,7 +435,7 @@ def config_c3_shape(seed: int = 2):
         ns = 3 if t in three else 2
         n_slots.append(ns)
         sizes.append([int(x) for x in raw[3 * t:3 * t + ns]])
-    _cap_total(n_slots, sizes, 30_000_000_000, 20)
+    _cap_total(n_slots, sizes, int(target), 20)
     sizes = [x for s in sizes for x in s]
     return n_slots, sizes
 
