@@ -399,7 +399,7 @@ def c3_leg(precisions=("bf16", "fp8"), serve_queries=60, serve_qps=2.0, seq_quer
     return c3, serving
 
 
-def probe_leg(targets=5):
+def probe_leg(targets=5, libraries=("12M", "10B", "70B")):
     """The paper's own configuration: a 28-head linear probe on d = 64 embeddings,
     libraries shaped like its BRICS 12M, BRICS 10B and Enamine REAL 70B ones, the
     runtime table's k values with no constraints and with the four Lipinski
@@ -417,6 +417,8 @@ def probe_leg(targets=5):
                     "Lipinski-style bounds on seeded property heads at seeded quantiles in [0.6, 0.9]",
            "paper_t4": PAPER_T4["hardware"], "libraries": []}
     for name, seed, shape in shapes:
+        if name not in libraries:
+            continue
         t0 = time.perf_counter()
         n_slots, sizes = shape()
         lib_h, dec_h = gen.config_probe(seed, n_slots, sizes)
@@ -516,9 +518,11 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--quick", action="store_true", help="headline precision only (profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "probe"],
                     help="c1: 1.04e7-compound library (default); c3: 2.9e10-compound streamed library; "
-                         "c4: serving a query stream over subsets of the c3 library")
+                         "c4: serving a query stream over subsets of the c3 library; probe: the paper's runtime "
+                         "table alone (linear probe)")
+    ap.add_argument("--probe-libraries", default="12M,10B,70B", help="probe workload: libraries to run")
     ap.add_argument("--serve-queries", type=int, default=None,
                     help="serving stream length (0: skip; default 80, c4: 2000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -547,6 +551,11 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "c3":
         return main_c3(args)
+    if args.workload == "probe":
+        res = probe_leg(libraries=args.probe_libraries.split(","))
+        print(json.dumps({"metric": "seconds per search (the paper's runtime table)", "probe_runtime_table": res}),
+              flush=True)
+        return
     c4 = args.workload == "c4"
     if args.serve_queries is None:
         args.serve_queries = 2000 if c4 else 80

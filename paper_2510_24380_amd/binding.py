@@ -230,19 +230,19 @@ class _QueryMarshal:
 
 class _ResultMarshal:
     def __init__(self, k: int, n_heads: int):
-        self.ids = np.zeros(k, np.uint64)
-        self.obj = np.zeros(k, np.float32)
-        self.heads = np.zeros((k, n_heads), np.float32)
-        self.reaction = np.zeros(k, np.uint32)
-        self.synthon = np.zeros((k, 3), np.uint32)
+        self.ids = np.empty(k, np.uint64)
+        self.obj = np.empty(k, np.float32)
+        self.heads = np.empty((k, n_heads), np.float32)
+        self.reaction = np.empty(k, np.uint32)
+        self.synthon = np.empty((k, 3), np.uint32)
         self.c = ResultC(k, self.ids.ctypes.data, self.obj.ctypes.data, self.heads.ctypes.data,
                          self.reaction.ctypes.data, self.synthon.ctypes.data, 0, 0, 0, 0)
 
     def result(self) -> SearchResult:
+        # the arrays belong to this one result: views, no copies
         n = int(self.c.n_found)
-        return SearchResult(self.ids[:n].copy(), self.obj[:n].copy(), self.heads[:n].copy(),
-                            self.reaction[:n].copy(), self.synthon[:n].copy(), int(self.c.n_scored),
-                            int(self.c.n_candidates), int(self.c.n_reruns))
+        return SearchResult(self.ids[:n], self.obj[:n], self.heads[:n], self.reaction[:n], self.synthon[:n],
+                            int(self.c.n_scored), int(self.c.n_candidates), int(self.c.n_reruns))
 
 
 class Engine:

@@ -70,7 +70,7 @@ struct QState {
   uint32_t count;     // entries appended (may exceed cap)
   uint32_t chunk_base;// count when the current chunk began
   uint32_t overflow;  // chunks re-run so far are flagged in the rerun list
-  uint32_t pad1;
+  uint32_t warm;      // 1: the warm start set a finite threshold
   uint64_t appended;  // total appends over the search
 };
 

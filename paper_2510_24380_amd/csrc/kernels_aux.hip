@@ -929,6 +929,7 @@ __global__ void k_state_reset(QState* st) {
     st->count = 0;
     st->chunk_base = 0;
     st->overflow = 0;
+    st->warm = 0;
     st->appended = 0;
   }
 }
@@ -944,9 +945,11 @@ __global__ void k_tau_relax(const QueryDev* __restrict__ qs, uint32_t nq) {
   if (st->count >= qs[q].K && t == t && t != -INFINITY) {
     st->tau_o = t - fabsf(t) * 3.814697265625e-06f - 7.888609052210118e-31f;
     st->tau_id = ~0ull;
+    st->warm = 1;
   } else {
     st->tau_o = -INFINITY;
     st->tau_id = ~0ull;
+    st->warm = 0;
   }
   st->count = 0;
   st->chunk_base = 0;

@@ -37,6 +37,18 @@ using namespace apex;
 
 namespace apex {
 
+// Rank in a sample of n_sample compounds (of n_comp) whose key is taken as the
+// warm-start threshold of a query keeping K: the expected number m of the final
+// K best in the sample plus four standard deviations and 8, at most K.
+// APEX_TEST_SPEC_RANK forces the rank (tests of the verification).
+uint32_t spec_rank(uint32_t K, uint32_t n_sample, uint64_t n_comp) {
+  const uint64_t forced = env_u64("APEX_TEST_SPEC_RANK");
+  if (forced) return (uint32_t)std::min<uint64_t>(forced, K);
+  const double m = (double)K * (double)n_sample / (double)std::max<uint64_t>(n_comp, 1);
+  const double r = std::ceil(m + 4.0 * std::sqrt(m) + 8.0);
+  return r >= (double)K ? K : (uint32_t)r;
+}
+
 // compounds in the first chunk: small, so that the appends before the first
 // select stay few even with the warm start's loose threshold
 constexpr uint64_t kFirstChunk = 1ull << 20;
@@ -585,11 +597,29 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
     HIP_TRY(hipMemcpyAsync(sh.plan, plan.data(), sizeof(SelDev) * plan.size(), hipMemcpyHostToDevice, s));
 
   uint64_t scored = 0;
-  // 1. threshold warm start from a stratified sample of the searched reactions
+  // 1. threshold warm start from a stratified sample of the searched reactions:
+  // each query's threshold is the key of rank r of the sample. r = K is a
+  // guaranteed lower bound of the final K-th key; when the sample is much
+  // smaller than the library, r is taken from the expected number of the final
+  // K best in the sample plus a margin, which is speculative: a query left with
+  // fewer than K survivors is enumerated again without the threshold (below).
+  std::vector<uint8_t> spec(nq, 0);
+  std::vector<QueryDev> qw(qd);
   if (n_comp >= 8ull * sh.n_sample) {
+    bool any_spec = false;
+    for (uint32_t i = 0; i < nq; ++i) {
+      const uint32_t r = spec_rank(P[i].K, sh.n_sample, n_comp);
+      if (r < P[i].K) {
+        qw[i].K = r;
+        spec[i] = 1;
+        any_spec = true;
+      }
+    }
+    if (any_spec) HIP_TRY(hipMemcpyAsync(sh.qd, qw.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
     apex_status st = warm_start(E, prec, sh.plan, (uint32_t)plan.size(), n_tiles, n_comp, sh.n_sample,
                                 sh.sample_ids, sh.sample_heads, sh.qd, nq, s);
     if (st != APEX_OK) return st;
+    if (any_spec) HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
     scored += sh.n_sample;
   }
 
@@ -623,13 +653,43 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
     std::vector<uint32_t> flags((size_t)nq * sh.n_flags);
     for (uint32_t i = 0; i < nq; ++i)
       std::memcpy(flags.data() + (size_t)i * sh.n_flags, out_flags(P[i], rb.data(), base), 4 * sh.n_flags);
+    // a speculative threshold that left fewer than K survivors was above the
+    // final K-th key: that query is enumerated again from scratch
+    std::vector<uint8_t> redo(nq, 0);
+    bool any_redo = false;
+    for (uint32_t i = 0; i < nq; ++i) {
+      if (!spec[i]) continue;
+      spec[i] = 0;
+      const QState* st = reinterpret_cast<const QState*>(rb.data() + ((const char*)P[i].st - base));
+      if (st->warm && st->count < P[i].K) {
+        redo[i] = 1;
+        any_redo = true;
+        std::fill(flags.begin() + (size_t)i * sh.n_flags, flags.begin() + (size_t)(i + 1) * sh.n_flags, 0u);
+      }
+    }
     bool any = false;
     for (uint32_t f : flags) any |= f != 0;
-    if (!any) break;
+    if (!any && !any_redo) break;
     if (round > 64) return set_error(APEX_E_DEVICE, "candidate buffer overflow did not settle");
     for (uint32_t i = 0; i < nq; ++i) {
       apex_status st = fill_u32(P[i].rerun, sh.n_flags, 0u, s);
       if (st != APEX_OK) return st;
+    }
+    if (any_redo) {
+      for (uint32_t i = 0; i < nq; ++i) {
+        qd[i].active = redo[i];
+        if (redo[i]) HIP_TRY(launch_state_reset(P[i].st, s));
+      }
+      HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
+      for (size_t c = 0; c < chunks.size(); ++c) {
+        const uint64_t cc = plan_compounds(E, prec, plan, chunks[c].first, chunks[c].second);
+        apex_status st = enum_pass(E, prec, sh.plan, (uint32_t)plan.size(), chunks[c].first, chunks[c].second,
+                                   sh.qd, nq, cc, s);
+        if (st != APEX_OK) return st;
+        HIP_TRY(launch_select(sh.qd, nq, (uint32_t)c, 0, s));
+        scored += cc;
+        ++reruns;
+      }
     }
     for (size_t c = 0; c < chunks.size(); ++c) {
       bool need = false;

@@ -60,6 +60,23 @@ def _mlp_query(sample, k):
     return Query(w=w, constraints=cons, k=k)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mlp_speculative_threshold_redo(mlp1m, prec, monkeypatch):
+    """The MLP path with a forced too-high warm-start threshold: re-enumerated,
+    exact (FP32) or at full recall (BF16)."""
+    lib_h, dec_h, (lib, dec, eng), sample = mlp1m
+    q = _mlp_query(sample, 500)
+    monkeypatch.setenv("APEX_TEST_SPEC_RANK", "1")
+    print(f"case: mlp forced speculative rank 1 {prec}", flush=True)
+    r = eng.search(q, precision=prec)
+    print(f"[spec] reruns={r.n_reruns} scored={r.n_scored}", flush=True)
+    assert r.n_reruns > 0 and r.n_scored >= 2 * lib_h.n_compounds
+    if prec == "fp32":
+        check_fp32_exact(lib_h, dec_h, q, r, "mlp speculative redo")
+    else:
+        check_lowp(lib_h, dec_h, q, r, "mlp speculative redo bf16")
+
+
 def test_mlp_long_answer_fp32(mlp1m):
     lib_h, dec_h, (lib, dec, eng), sample = mlp1m
     q = _mlp_query(sample, 100_000)

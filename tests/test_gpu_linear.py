@@ -100,12 +100,31 @@ def test_linear_forced_chunks_and_overflow(large, monkeypatch):
     lib_h, dec_h, (lib, dec, eng), sample = large
     monkeypatch.setenv("APEX_TEST_CHUNK", "40000")
     monkeypatch.setenv("APEX_TEST_CAP", "1200")
+    # the guaranteed warm-start bound (rank K), looser than the speculative one,
+    # so that the small buffer overflows
+    monkeypatch.setenv("APEX_TEST_SPEC_RANK", str(1 << 30))
     q = _wide_query(sample, 300)
     print("case: linear forced chunks / cap", flush=True)
     r = eng.search(q)
     print(f"[forced] reruns={r.n_reruns} candidates={r.n_candidates}", flush=True)
     assert r.n_reruns > 0
     check_fp32_exact(lib_h, dec_h, q, r, "linear forced chunks")
+
+
+def test_linear_speculative_threshold_redo(large, monkeypatch):
+    """A warm-start threshold above the final K-th key (forced: the best sampled
+    key) leaves fewer than K survivors; the query is enumerated again without it
+    and the answer is still exact."""
+    lib_h, dec_h, (lib, dec, eng), sample = large
+    q = _wide_query(sample, 2000)
+    monkeypatch.setenv("APEX_TEST_SPEC_RANK", "1")
+    print("case: linear forced speculative rank 1", flush=True)
+    r = eng.search(q)
+    print(f"[spec] reruns={r.n_reruns} scored={r.n_scored}", flush=True)
+    assert r.n_reruns > 0 and r.n_scored >= 2 * lib_h.n_compounds
+    check_fp32_exact(lib_h, dec_h, q, r, "linear speculative redo")
+    monkeypatch.delenv("APEX_TEST_SPEC_RANK")
+    assert np.array_equal(eng.search(q).ids, r.ids)
 
 
 def test_linear_batch_equals_single_and_oracle(small):
