@@ -164,7 +164,18 @@ typedef struct {
                                           candidates are rescored in FP32; 0 means 4 */
   uint32_t n_subset;                   /* 0 = whole library */
   const uint32_t* subset;              /* host [n_subset] distinct reaction indices */
+  uint32_t flags;                      /* APEX_QUERY_* */
 } apex_query;
+
+/* Query flag: the violation-ranked fallback (Section 4.3, the violation c(x)
+ * and the lexicographic queue over (c, objective) without its final removal of
+ * violators). When fewer than k compounds satisfy every bound, the remaining
+ * places go to the least-violating compounds, c(x) = -sum over constraints of
+ * max(0, lo - f) + max(0, f - hi), best (largest) c first; violators with equal
+ * c rank by lower id. Feasible compounds (c = 0) come first, by objective as
+ * without the flag. apex_search and apex_search_noalloc on one-layer
+ * (linear-probe) engines only; APEX_E_UNSUPPORTED elsewhere. */
+#define APEX_QUERY_KEEP_VIOLATORS 1u
 
 typedef struct {
   uint64_t capacity;    /* entries each array below can hold (>= k) */
@@ -177,6 +188,8 @@ typedef struct {
   uint64_t n_scored;    /* out: compounds the search evaluated */
   uint64_t n_candidates;/* out: candidate entries appended while streaming */
   uint32_t n_reruns;    /* out: chunks re-run after a candidate-buffer overflow */
+  float* violation;     /* host [capacity] or NULL: c(x) of each entry (0 when feasible);
+                           written for APEX_QUERY_KEEP_VIOLATORS queries */
 } apex_result;
 
 /* Device workspace a search of this query needs: candidate buffers, the pool,

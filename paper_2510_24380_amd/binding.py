@@ -22,6 +22,7 @@ APEX_OK = 0
 STATUS = {0: "APEX_OK", -1: "APEX_E_INVALID", -2: "APEX_E_NOMEM", -3: "APEX_E_DEVICE",
           -4: "APEX_E_UNSUPPORTED", -5: "APEX_E_PENDING", -6: "APEX_E_CANCELLED"}
 ACT = {"none": 0, "relu": 1, "silu": 2}
+APEX_QUERY_KEEP_VIOLATORS = 1
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 P = ctypes.c_void_p
@@ -50,13 +51,13 @@ class ConstraintC(ctypes.Structure):
 
 class QueryC(ctypes.Structure):
     _fields_ = [("objective_w", P), ("n_constraints", U32), ("constraints", P), ("k", U64),
-                ("precision", U32), ("pool_factor", U32), ("n_subset", U32), ("subset", P)]
+                ("precision", U32), ("pool_factor", U32), ("n_subset", U32), ("subset", P), ("flags", U32)]
 
 
 class ResultC(ctypes.Structure):
     _fields_ = [("capacity", U64), ("ids", P), ("objective", P), ("heads", P), ("reaction", P),
                 ("synthon", P), ("n_found", U64), ("n_scored", U64), ("n_candidates", U64),
-                ("n_reruns", U32)]
+                ("n_reruns", U32), ("violation", P)]
 
 
 class ServerConfigC(ctypes.Structure):
@@ -206,6 +207,7 @@ class SearchResult:
     n_scored: int
     n_candidates: int
     n_reruns: int
+    violation: Optional[np.ndarray] = None  # c(x) per entry (keep-violators queries)
 
 
 class _QueryMarshal:
@@ -223,9 +225,10 @@ class _QueryMarshal:
             self.cons[i] = ConstraintC(int(c.head), lo, hi)
         subset = getattr(q, "reactions", None)
         self.subset = np.ascontiguousarray(list(subset) if subset is not None else [0], dtype=np.uint32)
+        flags = APEX_QUERY_KEEP_VIOLATORS if getattr(q, "keep_violators", False) else 0
         self.c = QueryC(self.w.ctypes.data, len(cons), ctypes.cast(self.cons, P), int(q.k), PREC[precision],
                         int(pool_factor), len(subset) if subset is not None else 0,
-                        self.subset.ctypes.data if subset is not None else None)
+                        self.subset.ctypes.data if subset is not None else None, flags)
 
 
 class _ResultMarshal:
@@ -235,14 +238,15 @@ class _ResultMarshal:
         self.heads = np.empty((k, n_heads), np.float32)
         self.reaction = np.empty(k, np.uint32)
         self.synthon = np.empty((k, 3), np.uint32)
+        self.viol = np.empty(k, np.float32)
         self.c = ResultC(k, self.ids.ctypes.data, self.obj.ctypes.data, self.heads.ctypes.data,
-                         self.reaction.ctypes.data, self.synthon.ctypes.data, 0, 0, 0, 0)
+                         self.reaction.ctypes.data, self.synthon.ctypes.data, 0, 0, 0, 0, self.viol.ctypes.data)
 
     def result(self) -> SearchResult:
         # the arrays belong to this one result: views, no copies
         n = int(self.c.n_found)
         return SearchResult(self.ids[:n], self.obj[:n], self.heads[:n], self.reaction[:n], self.synthon[:n],
-                            int(self.c.n_scored), int(self.c.n_candidates), int(self.c.n_reruns))
+                            int(self.c.n_scored), int(self.c.n_candidates), int(self.c.n_reruns), self.viol[:n])
 
 
 class Engine:

@@ -96,13 +96,16 @@ struct SelScratch {
 // evaluated from per-row tables built once per query: column 0 holds each
 // synthon row's objective contribution sum_h w[h] v[h] (NaN if a head of the
 // row is not finite), column 1 + c the row's value of constrained head head[c].
+// Ordinary passes list the distinct constrained heads with their intersected
+// bounds; the violation pass (viol = 1) lists the query's constraints as given,
+// since the violation sums over constraints.
 struct ScalarQuery {
   float w[kScalarHeads];
-  uint32_t head[APEX_MAX_CONSTRAINTS];  // distinct constrained heads
-  float lo[APEX_MAX_CONSTRAINTS];       // intersected inclusive bounds per head
+  uint32_t head[APEX_MAX_CONSTRAINTS];  // constrained heads
+  float lo[APEX_MAX_CONSTRAINTS];       // inclusive bounds
   float hi[APEX_MAX_CONSTRAINTS];
-  uint32_t n_ch;                        // constrained heads
-  uint32_t pad;
+  uint32_t n_ch;                        // entries of head/lo/hi
+  uint32_t viol;                        // 1: rank infeasible compounds by violation
   float* tab;                           // [1 + n_ch][rows]
   uint64_t rows;
 };

@@ -61,6 +61,8 @@ hipError_t scan_prepare(int* max_wg_per_cu);
 hipError_t launch_scan(const EnumArgs& a, uint32_t grid_max, hipStream_t s);
 hipError_t launch_scan_list(const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq, const ReactDev* react,
                             uint32_t n_react, uint64_t n_total, hipStream_t s);
+hipError_t launch_viol_answer(const ScalarQuery* sq, const ReactDev* react, uint32_t n_react, const uint64_t* ids,
+                              const QState* st, uint32_t K, float* obj, float* viol, hipStream_t s);
 hipError_t launch_lin_heads(const float* V, uint32_t hs, const ReactDev* react, uint32_t n_react, uint64_t n_total,
                             const uint64_t* ids, uint32_t n, float* heads, hipStream_t s);
 

@@ -76,6 +76,22 @@ __device__ __forceinline__ T* uni_ptr(T* p) {
   return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
 }
 
+// Violation of compound (a, b), c = -(sum over constraints of max(0, lo - f) +
+// max(0, f - hi)), accumulated in constraint order (Section 4.3).
+__device__ __forceinline__ float scalar_violation(const ScalarQuery* __restrict__ sq, const ReactDev& R, uint32_t a,
+                                                  uint32_t b) {
+  const uint32_t nch = sq->n_ch;
+  const uint64_t rows = sq->rows;
+  float acc = 0.0f;
+  for (uint32_t c = 0; c < nch; ++c) {
+    const float* col = sq->tab + (uint64_t)(c + 1) * rows;
+    const float h = a_value(col, R, a) + col[R.rowB + b];
+    acc = acc + fmaxf(0.0f, sq->lo[c] - h);
+    acc = acc + fmaxf(0.0f, h - sq->hi[c]);
+  }
+  return -acc;
+}
+
 // Appends (o, id) of the lanes with pass set: one atomic per wave.
 __device__ __forceinline__ void wave_append(const QueryDev& Q, bool pass, float o, uint64_t id, int lane) {
   const uint64_t m = __ballot(pass);
@@ -137,6 +153,25 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
       const float tau_o = unif(Q.st->tau_o);
       const uint64_t tau_id = uni64(Q.st->tau_id);
       const float bo = b_ok ? col0[R.rowB + b] : __builtin_nanf("");
+      if (uni32(sq->viol)) {
+        // violation pass: every compound that violates a bound is ranked by its
+        // violation (key) against the query's threshold; its objective only
+        // needs to be finite
+        for (uint32_t al = 0; al < na; ++al) {
+          const uint32_t a = a0 + al;
+          const float o = a_value(col0, R, a) + bo;
+          bool pass = b_ok && finite_obj(o);
+          float cv = 0.0f;
+          if (pass) {
+            cv = scalar_violation(sq, R, a, b);
+            pass = cv < 0.0f;
+          }
+          const uint64_t id = R.id_off + (uint64_t)a * R.nB + b;
+          pass = pass && key_passes(cv, id, tau_o, tau_id);
+          wave_append(Q, pass, cv, id, lane);
+        }
+        continue;
+      }
       // the row of A values (NaN past the reaction's edge: never passes)
       __builtin_amdgcn_wave_barrier();
       row[lane] = (uint32_t)lane < na ? a_value(col0, R, a0 + (uint32_t)lane) : __builtin_nanf("");
@@ -194,10 +229,34 @@ __global__ __launch_bounds__(256) void k_scan_list(const uint64_t* __restrict__ 
       const uint32_t a = (uint32_t)(loc / R.nB), b = (uint32_t)(loc - (uint64_t)a * R.nB);
       const ScalarQuery* sq = Q.sq;
       o = canon_zero(a_value(sq->tab, R, a) + sq->tab[R.rowB + b]);
-      pass = finite_obj(o) && key_passes(o, id, Q.st->tau_o, Q.st->tau_id) && scalar_feasible(sq, R, a, b);
+      if (sq->viol) {
+        const bool fin = finite_obj(o);
+        o = fin ? scalar_violation(sq, R, a, b) : 0.0f;  // the key of the violation pass
+        pass = fin && o < 0.0f && key_passes(o, id, Q.st->tau_o, Q.st->tau_id);
+      } else {
+        pass = finite_obj(o) && key_passes(o, id, Q.st->tau_o, Q.st->tau_id) && scalar_feasible(sq, R, a, b);
+      }
     }
   }
   wave_append(Q, pass, o, id, lane);
+}
+
+// Answer of a violation pass: the sorted keys (violations) move to viol, and
+// the objective of each listed compound is recomputed with the enumeration's
+// arithmetic into obj. n = min(st->count, K) entries.
+__global__ __launch_bounds__(256) void k_viol_answer(const ScalarQuery* __restrict__ sq,
+                                                     const ReactDev* __restrict__ react, uint32_t n_react,
+                                                     const uint64_t* __restrict__ ids, const QState* __restrict__ st,
+                                                     uint32_t K, float* __restrict__ obj, float* __restrict__ viol) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= min(st->count, K)) return;
+  const uint64_t id = ids[i];
+  const uint32_t t = find_reaction(react, n_react, id);
+  const ReactDev R = react[t];
+  const uint64_t loc = id - R.id_off;
+  const uint32_t a = (uint32_t)(loc / R.nB), b = (uint32_t)(loc - (uint64_t)a * R.nB);
+  viol[i] = obj[i];
+  obj[i] = canon_zero(a_value(sq->tab, R, a) + sq->tab[R.rowB + b]);
 }
 
 // FP32 heads of listed compounds: heads[e * hs + h] for h < hs (zero columns
@@ -257,6 +316,13 @@ hipError_t launch_scan_list(const uint64_t* ids, uint32_t n, const QueryDev* qs,
   if (n == 0 || nq == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scan_list, dim3((n + 255) / 256, nq), dim3(256), 0, s, ids, n, qs, nq, react, n_react,
                      n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_viol_answer(const ScalarQuery* sq, const ReactDev* react, uint32_t n_react, const uint64_t* ids,
+                              const QState* st, uint32_t K, float* obj, float* viol, hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_viol_answer, dim3((K + 255) / 256), dim3(256), 0, s, sq, react, n_react, ids, st, K, obj, viol);
   return hipGetLastError();
 }
 

@@ -97,6 +97,9 @@ apex_status validate_query(const apex_engine* E, const apex_query* q) {
     if (std::isnan(k.lo) || std::isnan(k.hi)) return set_error(APEX_E_INVALID, "constraint %u: NaN bound", c);
     if (k.lo > k.hi) return set_error(APEX_E_INVALID, "constraint %u: lo > hi", c);
   }
+  if (q->flags & ~APEX_QUERY_KEEP_VIOLATORS) return set_error(APEX_E_INVALID, "unknown query flags 0x%x", q->flags);
+  if ((q->flags & APEX_QUERY_KEEP_VIOLATORS) && !E->scalar)
+    return set_error(APEX_E_UNSUPPORTED, "the violation-ranked fallback needs a one-layer (linear-probe) engine");
   if (q->n_subset) {
     if (!q->subset) return set_error(APEX_E_INVALID, "null subset");
     std::vector<uint8_t> seen(E->lib->T, 0);
@@ -135,10 +138,12 @@ void query_sizes(const apex_engine* E, const apex_query* q, QPlan& P) {
   P.k = (uint32_t)q->k;
   P.lowp = q->precision != APEX_PREC_FP32;
   P.hs = E->HS;
+  P.keep = (q->flags & APEX_QUERY_KEEP_VIOLATORS) != 0;
   if (E->scalar) {
     uint32_t head[APEX_MAX_CONSTRAINTS];
     float lo[APEX_MAX_CONSTRAINTS], hi[APEX_MAX_CONSTRAINTS];
     P.n_cols = 1 + constrained_heads(q, head, lo, hi);
+    if (P.keep) P.n_cols = 1 + q->n_constraints;  // the violation pass's columns (one per constraint)
     P.tab_rows = E->lib->rows;
   }
   const uint32_t pf = q->pool_factor ? q->pool_factor : 4;
@@ -190,6 +195,7 @@ void out_layout(Bump& b, QPlan& p) {
   p.fin_heads = b.take<float>((size_t)p.k * p.hs);
   p.fin_reaction = b.take<uint32_t>(p.k);
   p.fin_synthon = b.take<uint32_t>((size_t)p.k * 3);
+  if (p.keep) p.fin_c = b.take<float>(p.k);
   p.out_bytes = b.off - off0;
 }
 
@@ -310,7 +316,17 @@ apex_status query_device_init(const apex_engine* E, const apex_query* q, const Q
     // synthon's contribution to the objective, dotted once per query)
     ScalarQuery sq{};
     for (uint32_t h = 0; h < E->H; ++h) sq.w[h] = q->objective_w[h];
-    sq.n_ch = constrained_heads(q, sq.head, sq.lo, sq.hi);
+    if (P.viol) {
+      sq.viol = 1;
+      sq.n_ch = q->n_constraints;
+      for (uint32_t c = 0; c < q->n_constraints; ++c) {
+        sq.head[c] = q->constraints[c].head;
+        sq.lo[c] = q->constraints[c].lo;
+        sq.hi[c] = q->constraints[c].hi;
+      }
+    } else {
+      sq.n_ch = constrained_heads(q, sq.head, sq.lo, sq.hi);
+    }
     sq.tab = P.tab;
     sq.rows = P.tab_rows;
     HIP_TRY(hipMemcpyAsync(P.sq, &sq, sizeof(sq), hipMemcpyHostToDevice, s));
@@ -445,6 +461,8 @@ apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev
     } else {
       HIP_TRY(launch_rank_sort(qd_dev, 0, P.K, P.fin_o, P.fin_id, rank_scratch(P), s));
     }
+    if (P.viol)  // the sorted keys are violations: move them, recompute the objectives
+      HIP_TRY(launch_viol_answer(P.sq, E->react, E->lib->T, P.fin_id, P.st, P.K, P.fin_o, P.fin_c, s));
     // rows past the answer's length are computed from stale ids and never read
     apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, P.k, P.fin_heads, s);
     if (st != APEX_OK) return st;
@@ -497,6 +515,12 @@ void finish_read(const apex_engine* E, const QPlan& P, const char* host, const c
       std::memcpy(res->heads + (size_t)e * E->H, h + (size_t)e * P.hs, sizeof(float) * E->H);
   }
   if (res->reaction) std::memcpy(res->reaction, in_copy(host, base, P.fin_reaction), sizeof(uint32_t) * n_found);
+  if (res->violation && P.keep) {
+    if (P.viol)
+      std::memcpy(res->violation, in_copy(host, base, P.fin_c), sizeof(float) * n_found);
+    else
+      std::fill(res->violation, res->violation + n_found, 0.0f);
+  }
   if (res->synthon) std::memcpy(res->synthon, in_copy(host, base, P.fin_synthon), sizeof(uint32_t) * 3 * n_found);
 }
 
@@ -525,9 +549,12 @@ uint32_t sample_count(const std::vector<QPlan>& P) {
 }
 
 void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& b, std::vector<QPlan>& P,
-                  Shared& sh) {
+                  Shared& sh, bool viol = false) {
   P.assign(n, QPlan());
-  for (uint32_t i = 0; i < n; ++i) query_sizes(E, &qs[i], P[i]);
+  for (uint32_t i = 0; i < n; ++i) {
+    query_sizes(E, &qs[i], P[i]);
+    P[i].viol = viol;
+  }
   const int prec = (int)qs[0].precision;
   sh.n_flags = (uint32_t)chunk_schedule(E->prec[prec].full_tiles, tile_compounds(E->scalar)).size() + 1;
   sh.n_sample = sample_count(P);
@@ -544,7 +571,7 @@ void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& 
 }  // namespace
 
 static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq, void* ws, size_t ws_bytes,
-                              hipStream_t s, apex_result* res, bool pageable_readback = false) {
+                              hipStream_t s, apex_result* res, bool pageable_readback = false, bool viol = false) {
   if (!E || !qs || !res || nq == 0) return set_error(APEX_E_INVALID, "null argument");
   if (nq > APEX_MAX_FUSED_QUERIES) return set_error(APEX_E_INVALID, "%u queries > %d", nq, APEX_MAX_FUSED_QUERIES);
   for (uint32_t i = 0; i < nq; ++i) {
@@ -552,6 +579,8 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
     if (st != APEX_OK) return st;
     if (qs[i].precision != qs[0].precision)
       return set_error(APEX_E_INVALID, "fused queries must share one precision");
+    if (nq > 1 && (qs[i].flags & APEX_QUERY_KEEP_VIOLATORS))
+      return set_error(APEX_E_UNSUPPORTED, "the violation-ranked fallback runs one query at a time");
     if (res[i].capacity < qs[i].k || !res[i].ids || !res[i].objective)
       return set_error(APEX_E_INVALID, "result %u: capacity < k or null ids/objective", i);
   }
@@ -564,12 +593,12 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   Shared sh;
   {
     Bump b(nullptr);
-    batch_layout(E, qs, nq, b, P, sh);
+    batch_layout(E, qs, nq, b, P, sh, viol);
     if (b.off > ws_bytes)
       return set_error(APEX_E_NOMEM, "query workspace %zu bytes < %zu needed", ws_bytes, b.off);
   }
   Bump b(ws);
-  batch_layout(E, qs, nq, b, P, sh);
+  batch_layout(E, qs, nq, b, P, sh, viol);
 
   // reactions searched by at least one query
   std::vector<uint8_t> want(L->T, 0);
@@ -740,9 +769,37 @@ extern "C" apex_status apex_batch_workspace_size(const apex_engine* eng, const a
   return APEX_OK;
 }
 
+// One query; with APEX_QUERY_KEEP_VIOLATORS and fewer than k feasible
+// compounds, a second pass ranks the violating compounds by their violation
+// (the queue of Section 4.3 without its final removal) and fills the rest of
+// the answer with the best of them.
+static apex_status search_one(apex_engine* E, const apex_query* q, void* ws, size_t ws_bytes, hipStream_t s,
+                              apex_result* res, bool pageable) {
+  apex_status st = run_search(E, q, 1, ws, ws_bytes, s, res, pageable, false);
+  if (st != APEX_OK || !(q->flags & APEX_QUERY_KEEP_VIOLATORS) || res->n_found >= q->k) return st;
+  const uint64_t nf = res->n_found;
+  apex_query q2 = *q;
+  q2.k = q->k - nf;
+  apex_result r2{};
+  r2.capacity = q2.k;
+  r2.ids = res->ids + nf;
+  r2.objective = res->objective + nf;
+  r2.heads = res->heads ? res->heads + nf * E->H : nullptr;
+  r2.reaction = res->reaction ? res->reaction + nf : nullptr;
+  r2.synthon = res->synthon ? res->synthon + nf * 3 : nullptr;
+  r2.violation = res->violation ? res->violation + nf : nullptr;
+  st = run_search(E, &q2, 1, ws, ws_bytes, s, &r2, pageable, true);
+  if (st != APEX_OK) return st;
+  res->n_found = nf + r2.n_found;
+  res->n_scored += r2.n_scored;
+  res->n_candidates += r2.n_candidates;
+  res->n_reruns += r2.n_reruns;
+  return APEX_OK;
+}
+
 extern "C" apex_status apex_search(apex_engine* eng, const apex_query* q, void* workspace, size_t workspace_bytes,
                                    void* stream, apex_result* result) {
-  return run_search(eng, q, 1, workspace, workspace_bytes, (hipStream_t)stream, result);
+  return search_one(eng, q, workspace, workspace_bytes, (hipStream_t)stream, result, false);
 }
 
 extern "C" apex_status apex_search_batch(apex_engine* eng, const apex_query* qs, uint32_t n, void* workspace,
@@ -809,5 +866,5 @@ extern "C" apex_status apex_search_noalloc(apex_engine* eng, const apex_query* q
   void* ws = nullptr;
   st = static_scratch(dev, &ws);
   if (st != APEX_OK) return st;
-  return run_search(eng, q, 1, ws, APEX_STATIC_SCRATCH_BYTES, (hipStream_t)stream, result, true);
+  return search_one(eng, q, ws, APEX_STATIC_SCRATCH_BYTES, (hipStream_t)stream, result, true);
 }

@@ -32,6 +32,9 @@ struct QPlan {
   ScalarQuery* sq = nullptr;      // linear-probe engines: the query's tables
   float* tab = nullptr;
   uint32_t* rs_hist = nullptr;    // radix-sort scratch (answers above kSortSmallMax entries)
+  bool keep = false;              // APEX_QUERY_KEEP_VIOLATORS: layout fits the violation pass too
+  bool viol = false;              // this run is the violation pass
+  float* fin_c = nullptr;         // violation pass: the answer's violations
   char* out = nullptr;
   size_t out_bytes = 0;
   QState* st = nullptr;

@@ -549,6 +549,8 @@ extern "C" apex_status apex_server_submit(apex_server* srv, const apex_query* q,
   if (!srv || !q || !ticket) return set_error(APEX_E_INVALID, "null argument");
   apex_status st = validate_query(srv->E, q);
   if (st != APEX_OK) return st;
+  if (q->flags & APEX_QUERY_KEEP_VIOLATORS)
+    return set_error(APEX_E_UNSUPPORTED, "the violation-ranked fallback is not served; use apex_search");
   auto sq = std::make_shared<SQ>();
   sq->q = *q;
   sq->w.assign(q->objective_w, q->objective_w + srv->E->H);

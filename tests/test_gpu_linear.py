@@ -127,6 +127,75 @@ def test_linear_speculative_threshold_redo(large, monkeypatch):
     assert np.array_equal(eng.search(q).ids, r.ids)
 
 
+def _violation64(lib_h, dec_h, q, ids):
+    h = oracle.heads(lib_h, dec_h, np.asarray(ids, np.uint64))
+    c = np.zeros(len(ids))
+    for k in q.constraints:
+        c -= np.maximum(0.0, k.lo - h[:, k.head]) + np.maximum(0.0, h[:, k.head] - k.hi)
+    return c
+
+
+def _check_keep_violators(lib_h, dec_h, q, r, sample, label):
+    """Feasible compounds first (the exact feasible top-k), then violators by
+    violation, against the oracle's lexicographic queue kept without its final
+    removal (Section 4.3)."""
+    ids, o, c = oracle.topk_lex(lib_h, dec_h, q, keep_violators=True, with_violation=True)
+    nf = int(np.sum(c == 0.0))
+    print(f"[{label}] feasible={nf} answer={len(ids)} gpu={len(r.ids)}", flush=True)
+    assert len(r.ids) == len(ids)
+    assert np.all(r.violation[:nf] == 0.0) and np.all(r.violation[nf:] < 0.0)
+    scale = float(np.max(np.sqrt(np.mean(sample ** 2, axis=0))))
+    tol = 1e-5 * np.maximum(np.abs(c[nf:]), scale)
+    # the feasible part is the ordinary answer
+    assert set(r.ids[:nf].tolist()) == set(ids[:nf].tolist()), f"{label}: feasible part"
+    # violators: same ids unless their violations sit within FP32 error of the cut
+    got, want = set(r.ids[nf:].tolist()), set(ids[nf:].tolist())
+    if got != want:
+        diff = np.array(sorted(got ^ want), np.uint64)
+        cd = _violation64(lib_h, dec_h, q, diff)
+        assert np.all(np.abs(cd - c[-1]) <= 4 * 1e-5 * scale), f"{label}: violators differ away from the cut"
+        print(f"[{label}] {len(diff)} violators differ, all within FP32 error of the cut", flush=True)
+    c_gpu64 = _violation64(lib_h, dec_h, q, r.ids[nf:])
+    assert np.all(np.abs(r.violation[nf:] - c_gpu64) <= 1e-5 * np.maximum(np.abs(c_gpu64), scale)), label
+    assert np.all(np.diff(r.violation[nf:].astype(np.float64)) <= 0.0), f"{label}: violation order"
+    h64 = oracle.heads(lib_h, dec_h, r.ids)
+    o64 = h64 @ np.asarray(q.w, np.float64)
+    oscale = float(np.sqrt(np.mean((sample @ np.asarray(q.w, np.float64)) ** 2)))
+    assert np.all(np.abs(r.objective - o64) <= 1e-5 * np.maximum(np.abs(o64), oscale)), f"{label}: objectives"
+    assert np.all(np.abs(r.heads - h64) <= 1e-5 * np.maximum(np.abs(h64), scale)), f"{label}: heads"
+
+
+def _stringent(sample, k, keep=True):
+    qf = _quantile(sample)
+    w = g.normal_f32(59, "probe_w3", H)
+    cons = [Constraint(3, -math.inf, float(np.float32(qf(3, 0.05)))),
+            Constraint(11, float(np.float32(qf(11, 0.9))), math.inf),
+            Constraint(11, -math.inf, float(np.float32(qf(11, 0.97)))),
+            Constraint(22, float(np.float32(qf(22, 0.4))), float(np.float32(qf(22, 0.6))))]
+    return Query(w=w, constraints=cons, k=k, keep_violators=keep)
+
+
+@pytest.mark.parametrize("k", [40, 600])
+def test_linear_keep_violators(small, k):
+    lib_h, dec_h, (lib, dec, eng), sample = small
+    q = _stringent(sample, k)
+    print(f"case: linear keep violators k={k}", flush=True)
+    r = eng.search(q)
+    _check_keep_violators(lib_h, dec_h, q, r, sample, f"keep violators k={k}")
+    plain = eng.search(_stringent(sample, k, keep=False))
+    nf = len(plain.ids)
+    assert np.array_equal(r.ids[:nf], plain.ids) and np.array_equal(r.objective[:nf], plain.objective)
+
+
+def test_linear_keep_violators_warm_start(large):
+    """The violation pass over a library large enough for its own warm start."""
+    lib_h, dec_h, (lib, dec, eng), sample = large
+    q = _stringent(sample, 1500)
+    print("case: linear keep violators (warm start)", flush=True)
+    r = eng.search(q)
+    _check_keep_violators(lib_h, dec_h, q, r, sample, "keep violators large")
+
+
 def test_linear_batch_equals_single_and_oracle(small):
     lib_h, dec_h, (lib, dec, eng), sample = small
     qs = [_wide_query(sample, 40), _wide_query(sample, 500, reactions=[1, 3]),

@@ -270,6 +270,7 @@ class Query:
     constraints: List[Constraint]
     k: int
     reactions: Optional[Sequence[int]] = None
+    keep_violators: bool = False  # fill the answer with the least-violating compounds
 
 
 # ----------------------------------------------------------------------------
