@@ -10,4 +10,5 @@ from .oracle import (  # noqa: F401
     topk,
     topk_lex,
     TopK,
+    assoc_embeddings,
 )

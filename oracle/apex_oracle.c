@@ -610,3 +610,31 @@ int orc_topk_lex(const orc_library* L, const orc_decoder* dec, const orc_query* 
   free(offset);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Associative embeddings (Section 4.2, eq. "assoc_embeds"): every R-group r  */
+/* (a reaction's slot) has a key matrix K_r (d x dU) and every synthon s a     */
+/* value vector v_s (dU); the table row of (r, s) is u_{r,s} = K_r v_s. Rows   */
+/* are produced in (reaction, slot, synthon) order, the order the library     */
+/* tables use. keys: [n_slot_total][d][dU], values: [rows][dU] (float32),      */
+/* out: [rows][d] (double). Plain loops, the sum over the value index in      */
+/* ascending order.                                                           */
+/* ------------------------------------------------------------------------ */
+int orc_assoc_embeddings(uint32_t n_reactions, const uint32_t* n_slots, const uint32_t* slot_sizes, uint32_t d,
+                         uint32_t dU, const float* keys, const float* values, double* out) {
+  uint64_t slot = 0, row = 0;
+  for (uint32_t t = 0; t < n_reactions; t++) {
+    for (uint32_t s = 0; s < n_slots[t]; s++, slot++) {
+      const float* K = keys + slot * (uint64_t)d * dU;
+      for (uint32_t i = 0; i < slot_sizes[slot]; i++, row++) {
+        const float* v = values + row * dU;
+        for (uint32_t j = 0; j < d; j++) {
+          double u = 0.0;
+          for (uint32_t k = 0; k < dU; k++) u += (double)K[(uint64_t)j * dU + k] * (double)v[k];
+          out[row * d + j] = u;
+        }
+      }
+    }
+  }
+  return 0;
+}

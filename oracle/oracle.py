@@ -71,6 +71,8 @@ def _load():
         lib.orc_topk.restype = ctypes.c_int
         lib.orc_topk_lex.argtypes = [P, P, P, ctypes.c_int, P, P, P, P]
         lib.orc_topk_lex.restype = ctypes.c_int
+        lib.orc_assoc_embeddings.argtypes = [ctypes.c_uint32, P, P, ctypes.c_uint32, ctypes.c_uint32, P, P, P]
+        lib.orc_assoc_embeddings.restype = ctypes.c_int
         lib.orc_max_threads.argtypes = []
         lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -218,3 +220,18 @@ def topk_lex(lib, dec, q, keep_violators: bool = False, with_violation: bool = F
                          ids.ctypes.data, o.ctypes.data, c.ctypes.data, ctypes.byref(n))
     out = (ids[:n.value].copy(), o[:n.value].copy())
     return out + (c[:n.value].copy(),) if with_violation else out
+
+
+def assoc_embeddings(n_slots, slot_sizes, keys, values) -> np.ndarray:
+    """u_{r,s} = K_r v_s for every (reaction, slot, synthon) row, FP64
+    (Section 4.2, eq. "assoc_embeds"). keys: [n_slot_total, d, dU] float32,
+    values: [rows, dU] float32; returns [rows, d] float64."""
+    ns = np.ascontiguousarray(n_slots, dtype=np.uint32)
+    ss = np.ascontiguousarray(slot_sizes, dtype=np.uint32)
+    K = np.ascontiguousarray(keys, dtype=np.float32)
+    V = np.ascontiguousarray(values, dtype=np.float32)
+    assert K.ndim == 3 and K.shape[0] == ss.size and V.shape == (int(ss.sum()), K.shape[2])
+    out = np.zeros((V.shape[0], K.shape[1]), dtype=np.float64)
+    _load().orc_assoc_embeddings(ns.size, ns.ctypes.data, ss.ctypes.data, K.shape[1], K.shape[2], K.ctypes.data,
+                                 V.ctypes.data, out.ctypes.data)
+    return out

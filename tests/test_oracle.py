@@ -413,3 +413,47 @@ def test_violation_ranked_fallback_brute_force(k):
     m = min(k, n_feas)
     assert ids[:m].tolist() == r.answer_ids.tolist()
     assert np.all(c[:m] == 0.0) and np.all(c[m:] < 0.0)
+
+
+# ----------------------------------------------------------------------------
+# Associative embeddings (Section 4.2, eq. "assoc_embeds")
+# ----------------------------------------------------------------------------
+def test_assoc_worked_example():
+    """A hand-worked case (tests/golden/assoc_worked_example.json): distinct,
+    non-square key matrices per R-group, so a transposed key, a swapped slot or
+    a dropped term changes the result."""
+    ex = json.load(open(os.path.join(GOLDEN, "assoc_worked_example.json")))
+    u = oracle.assoc_embeddings(ex["n_slots"], ex["slot_sizes"], np.array(ex["keys"], np.float32),
+                                np.array(ex["values"], np.float32))
+    assert np.array_equal(u, np.array(ex["expected"], np.float64))
+
+
+def test_assoc_identity_scaling_and_permutation():
+    """Identity keys return the values; doubling a key doubles its rows exactly;
+    permuting the synthons of a slot permutes its rows; the map is linear in
+    the values."""
+    ns, ss = [2, 3], [4, 3, 2, 5, 3]
+    rows, d = sum(ss), 6
+    V = g.normal_f32(70, "assoc_v", rows * d).reshape(rows, d)
+    eye = np.repeat(np.eye(d, dtype=np.float32)[None], len(ss), axis=0)
+    assert np.array_equal(oracle.assoc_embeddings(ns, ss, eye, V), V.astype(np.float64))
+    dU = 4
+    K = g.normal_f32(71, "assoc_k", len(ss) * d * dU).reshape(len(ss), d, dU)
+    V = g.normal_f32(72, "assoc_v2", rows * dU).reshape(rows, dU)
+    u = oracle.assoc_embeddings(ns, ss, K, V)
+    K2 = K.copy()
+    K2[3] *= 2
+    u2 = oracle.assoc_embeddings(ns, ss, K2, V)
+    base = np.cumsum([0] + ss)
+    r3 = slice(base[3], base[4])
+    assert np.array_equal(u2[r3], 2 * u[r3])
+    mask = np.ones(rows, bool)
+    mask[r3] = False
+    assert np.array_equal(u2[mask], u[mask])
+    perm = np.array([2, 0, 4, 1, 3])
+    Vp = V.copy()
+    Vp[r3] = V[r3][perm]
+    assert np.array_equal(oracle.assoc_embeddings(ns, ss, K, Vp)[r3], u[r3][perm])
+    Va = g.normal_f32(73, "assoc_v3", rows * dU).reshape(rows, dU)
+    lin = oracle.assoc_embeddings(ns, ss, K, (V.astype(np.float64) + Va).astype(np.float32))
+    assert np.allclose(lin, u + oracle.assoc_embeddings(ns, ss, K, Va), rtol=1e-6, atol=1e-6)
