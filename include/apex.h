@@ -99,6 +99,24 @@ apex_status apex_library_num_compounds(const apex_library* lib, uint64_t* out);
 apex_status apex_decode_ids(const apex_library* lib, const uint64_t* ids, size_t n, uint32_t* reaction,
                             uint32_t* synthon);
 
+/* Associative embeddings (Section 4.2, eq. "assoc_embeds"), the step that
+ * produces the library tables: for R-group r (slot s of reaction t, in
+ * (reaction, slot) order) with key matrix K_r (d x dU) and each of its synthons
+ * with value vector v (dU), the table row is u = K_r v. Run per R-group as one
+ * grouped GEMM on the FP32 matrix cores (FP32 accumulation). The library gives
+ * the shape (slot sizes, d); its own tables are not read, so `out` may be the
+ * very buffer the library was created over (then create engines after this).
+ * keys: device [n_slots_total x d x dU] FP32 row-major; values: device
+ * [rows x dU] FP32, rows in (reaction, slot, synthon) order; out: device
+ * [rows x d] FP32. workspace: device, >= apex_assoc_workspace_size bytes,
+ * 256-byte aligned. Synchronous on `stream`. Errors: APEX_E_INVALID (null
+ * pointers, misaligned workspace), APEX_E_NOMEM (workspace too small),
+ * APEX_E_UNSUPPORTED (dU outside 1..APEX_MAX_ASSOC_DU), APEX_E_DEVICE. */
+#define APEX_MAX_ASSOC_DU 256
+apex_status apex_assoc_workspace_size(const apex_library* lib, size_t* bytes);
+apex_status apex_assoc_embeddings(const apex_library* lib, uint32_t dU, const float* keys, const float* values,
+                                  float* out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Decoder (eq. "surrogate" and its MLP generalisation)                      */
 /* ------------------------------------------------------------------------ */
@@ -277,6 +295,23 @@ apex_status apex_server_destroy(apex_server* srv);
  * pointers, precision not enabled), APEX_E_DEVICE. */
 apex_status apex_engine_heads(apex_engine* eng, const uint64_t* ids, uint32_t n, uint32_t precision, float* heads,
                               void* stream);
+
+/* Quantiles of the FP32 heads over compounds of the library: the percentile
+ * thresholds of counter-screening queries (Appendix A.11: e.g. every off-target
+ * docking score above its 50th percentile). ids: device [n] compound ids, or
+ * NULL for n compounds the engine draws itself (a seeded stratified sample of
+ * the whole library, distinct when n is at most the library size);
+ * 1 <= n <= APEX_MAX_QUANTILE_COMPOUNDS. levels: host [n_levels] in [0, 1],
+ * n_levels <= APEX_MAX_QUANTILE_LEVELS. out: host [n_levels x H]:
+ * out[l * H + h] is the levels[l] quantile of head h over the compounds whose
+ * head h is finite (linear interpolation between closest ranks, position
+ * levels[l] * (n_finite - 1); NaN if none is finite). Uses scratch inside the
+ * engine workspace: not safe concurrently with another quantile call on the
+ * same engine. Synchronous on `stream`. Errors: APEX_E_INVALID, APEX_E_DEVICE. */
+#define APEX_MAX_QUANTILE_COMPOUNDS 8192
+#define APEX_MAX_QUANTILE_LEVELS 256
+apex_status apex_engine_head_quantiles(apex_engine* eng, const uint64_t* ids, uint32_t n, const float* levels,
+                                       uint32_t n_levels, float* out, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing                                                             */

@@ -78,6 +78,8 @@ _SIGS = {
     "apex_library_create": [P, P],
     "apex_library_destroy": [P],
     "apex_library_num_compounds": [P, P],
+    "apex_assoc_workspace_size": [P, P],
+    "apex_assoc_embeddings": [P, U32, P, P, P, P, ctypes.c_size_t, P],
     "apex_decode_ids": [P, P, ctypes.c_size_t, P, P],
     "apex_decoder_create": [P, P],
     "apex_decoder_destroy": [P],
@@ -91,6 +93,7 @@ _SIGS = {
     "apex_search_batch": [P, P, U32, P, ctypes.c_size_t, P, P],
     "apex_engine_profile": [P, ctypes.c_int, P, P, P],
     "apex_engine_heads": [P, P, U32, U32, P, P],
+    "apex_engine_head_quantiles": [P, P, U32, P, U32, P, P],
     "apex_server_create": [P, P, P],
     "apex_server_submit": [P, P, P],
     "apex_server_poll": [P, U64, P, ctypes.c_int],
@@ -157,6 +160,22 @@ class Library:
         n = U64()
         _check(lib().apex_library_num_compounds(self.handle, ctypes.byref(n)))
         return int(n.value)
+
+    def assoc_embeddings(self, keys: torch.Tensor, values: torch.Tensor, out: Optional[torch.Tensor] = None,
+                         stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """u_{r,s} = K_r v_s for every table row (apex_assoc_embeddings): keys
+        [n_slots_total, d, dU], values [rows, dU] (device FP32). Writes `out`
+        (default: this library's own tables) and returns it."""
+        for t in (keys, values):
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("keys and values must be contiguous float32 device tensors")
+        out = self.tables if out is None else out
+        n = ctypes.c_size_t()
+        _check(lib().apex_assoc_workspace_size(self.handle, ctypes.byref(n)))
+        ws = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=keys.device)
+        _check(lib().apex_assoc_embeddings(self.handle, int(keys.shape[2]), keys.data_ptr(), values.data_ptr(),
+                                           out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+        return out
 
     def decode(self, ids):
         ids = np.ascontiguousarray(ids, dtype=np.uint64)
@@ -323,6 +342,20 @@ class Engine:
                                        _stream_ptr(stream)))
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         return out[:len(ids), :self.n_heads].cpu().numpy()
+
+    def head_quantiles(self, levels, n: int = 8192, ids=None,
+                       stream: Optional[torch.cuda.Stream] = None) -> np.ndarray:
+        """[len(levels), H] quantiles of the FP32 heads over n compounds drawn by
+        the engine (or the listed ids): percentile thresholds for queries."""
+        lv = np.ascontiguousarray(levels, dtype=np.float32)
+        out = np.empty((lv.size, self.n_heads), np.float32)
+        ids_d = None
+        if ids is not None:
+            ids_d = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int64)).cuda()
+            n = len(ids)
+        _check(lib().apex_engine_head_quantiles(self.handle, ids_d.data_ptr() if ids_d is not None else None, int(n),
+                                                lv.ctypes.data, lv.size, out.ctypes.data, _stream_ptr(stream)))
+        return out
 
     def profile(self, enable: bool):
         """Returns (ms, launches, compounds) timed since the last call, then

@@ -110,6 +110,15 @@ struct ScalarQuery {
   uint64_t rows;
 };
 
+// One R-group (slot) of the associative-embedding GEMM: its first table row,
+// its synthon count and its first 16-row tile in the grouped launch.
+struct AssocSlot {
+  uint64_t row0;
+  uint64_t tile0;
+  uint32_t n;
+  uint32_t pad;
+};
+
 // Query parameters for the fused kernel and the scoring kernels.
 struct QueryDev {
   float w[kHeadsPad];

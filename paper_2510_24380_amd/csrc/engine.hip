@@ -145,6 +145,44 @@ extern "C" apex_status apex_decode_ids(const apex_library* lib, const uint64_t* 
 }
 
 // ---------------------------------------------------------------------------
+// associative embeddings (Section 4.2, eq. "assoc_embeds")
+// ---------------------------------------------------------------------------
+extern "C" apex_status apex_assoc_workspace_size(const apex_library* lib, size_t* bytes) {
+  if (!lib || !bytes) return set_error(APEX_E_INVALID, "null argument");
+  *bytes = (sizeof(AssocSlot) * lib->slot_sizes.size() + 255) & ~(size_t)255;
+  return APEX_OK;
+}
+
+extern "C" apex_status apex_assoc_embeddings(const apex_library* lib, uint32_t dU, const float* keys,
+                                             const float* values, float* out, void* workspace, size_t workspace_bytes,
+                                             void* stream) {
+  if (!lib || !keys || !values || !out || !workspace) return set_error(APEX_E_INVALID, "null argument");
+  if (dU == 0 || dU > APEX_MAX_ASSOC_DU) return set_error(APEX_E_UNSUPPORTED, "dU = %u (1..%d)", dU, APEX_MAX_ASSOC_DU);
+  size_t need = 0;
+  apex_assoc_workspace_size(lib, &need);
+  if (workspace_bytes < need) return set_error(APEX_E_NOMEM, "workspace %zu bytes < %zu needed", workspace_bytes, need);
+  if (((uintptr_t)workspace) & 255) return set_error(APEX_E_INVALID, "workspace must be 256-byte aligned");
+  const size_t ns = lib->slot_sizes.size();
+  std::vector<AssocSlot> slots(ns);
+  uint64_t tiles = 0;
+  for (size_t j = 0; j < ns; ++j) {
+    slots[j].row0 = lib->row_base[j];
+    slots[j].n = lib->slot_sizes[j];
+    slots[j].tile0 = tiles;
+    tiles += (lib->slot_sizes[j] + 15) / 16;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, n_cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  auto* dslots = reinterpret_cast<AssocSlot*>(workspace);
+  HIP_TRY(hipMemcpyAsync(dslots, slots.data(), sizeof(AssocSlot) * ns, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_assoc(dslots, (uint32_t)ns, tiles, lib->d, dU, keys, values, out, n_cu, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return APEX_OK;
+}
+
+// ---------------------------------------------------------------------------
 // decoder
 // ---------------------------------------------------------------------------
 extern "C" apex_status apex_decoder_create(const apex_decoder_desc* desc, apex_decoder** out) {
@@ -224,6 +262,10 @@ void engine_layout(apex_engine* E, const apex_library* L, const apex_decoder* D,
   E->cal_ids = b.take<uint64_t>(kCalSamples);
   E->cal_h32 = b.take<float>((size_t)kCalSamples * kHeadsPad);
   E->cal_hlp = b.take<float>((size_t)kCalSamples * kHeadsPad);
+  E->qnt_ids = b.take<uint64_t>(APEX_MAX_QUANTILE_COMPOUNDS);
+  E->qnt_heads = b.take<float>((size_t)APEX_MAX_QUANTILE_COMPOUNDS * kScalarHeads);
+  E->qnt_levels = b.take<float>(APEX_MAX_QUANTILE_LEVELS);
+  E->qnt_out = b.take<float>((size_t)APEX_MAX_QUANTILE_LEVELS * kScalarHeads);
   for (int p = 0; p < 3; ++p) {
     PrecState& S = E->prec[p];
     S.on = (mask >> p) & 1u;
@@ -493,6 +535,32 @@ extern "C" apex_status apex_engine_create(apex_library* lib, apex_decoder* dec, 
 
 extern "C" apex_status apex_engine_destroy(apex_engine* eng) {
   delete eng;
+  return APEX_OK;
+}
+
+extern "C" apex_status apex_engine_head_quantiles(apex_engine* eng, const uint64_t* ids, uint32_t n,
+                                                  const float* levels, uint32_t n_levels, float* out, void* stream) {
+  if (!eng || !levels || !out) return set_error(APEX_E_INVALID, "null argument");
+  if (n == 0 || n > APEX_MAX_QUANTILE_COMPOUNDS)
+    return set_error(APEX_E_INVALID, "n = %u compounds (1..%d)", n, APEX_MAX_QUANTILE_COMPOUNDS);
+  if (n_levels == 0 || n_levels > APEX_MAX_QUANTILE_LEVELS)
+    return set_error(APEX_E_INVALID, "n_levels = %u (1..%d)", n_levels, APEX_MAX_QUANTILE_LEVELS);
+  for (uint32_t l = 0; l < n_levels; ++l)
+    if (!(levels[l] >= 0.0f && levels[l] <= 1.0f)) return set_error(APEX_E_INVALID, "level %u outside [0, 1]", l);
+  hipStream_t s = (hipStream_t)stream;
+  apex_engine* E = eng;
+  const uint64_t* dev_ids = ids;
+  if (!ids) {
+    HIP_TRY(launch_sample_ids(E->prec[APEX_PREC_FP32].plan, E->lib->T, E->react, E->lib->total, n, 0x9e3779b1ull,
+                              E->qnt_ids, s));
+    dev_ids = E->qnt_ids;
+  }
+  apex_status st = engine_gather(E, APEX_PREC_FP32, dev_ids, n, E->qnt_heads, s);
+  if (st != APEX_OK) return st;
+  HIP_TRY(hipMemcpyAsync(E->qnt_levels, levels, sizeof(float) * n_levels, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_head_quantiles(E->qnt_heads, E->HS, n, E->qnt_levels, n_levels, E->H, E->qnt_out, s));
+  HIP_TRY(hipMemcpyAsync(out, E->qnt_out, sizeof(float) * n_levels * E->H, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return APEX_OK;
 }
 

@@ -72,6 +72,11 @@ struct apex_engine {
   uint64_t* cal_ids = nullptr;
   float* cal_h32 = nullptr;
   float* cal_hlp = nullptr;
+  // head quantiles (apex_engine_head_quantiles)
+  uint64_t* qnt_ids = nullptr;
+  float* qnt_heads = nullptr;
+  float* qnt_levels = nullptr;
+  float* qnt_out = nullptr;
   apex::PrecState prec[3];
   std::vector<apex::ReactDev> react_host;
   // optional timing of the fused enumeration kernel (HIP events on the search stream)

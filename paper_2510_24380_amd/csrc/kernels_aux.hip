@@ -1004,55 +1004,6 @@ __global__ __launch_bounds__(kRankBlock) void k_rank_scatter(const QueryDev* __r
   }
 }
 
-// Sort n = min(count, K) entries by (objective desc, id asc): each entry's rank is
-// the number of entries ranked before it (keys are distinct).
-__global__ __launch_bounds__(256) void k_rank_sort(const QueryDev* __restrict__ qs, uint32_t q, float* __restrict__ out_o,
-                                                   uint64_t* __restrict__ out_id) {
-  const QueryDev& Q = qs[q];
-  const uint32_t n = min(Q.st->count, Q.K);
-  constexpr uint32_t TILE = 1024;
-  __shared__ __attribute__((aligned(16))) float so[TILE];
-  __shared__ __attribute__((aligned(16))) uint64_t sid[TILE];
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool mine = i < n;
-  const float o = mine ? Q.cand_o[i] : 0.0f;
-  const uint64_t id = mine ? Q.cand_id[i] : 0;
-  uint32_t rank = 0;
-  for (uint32_t t0 = 0; t0 < n; t0 += TILE) {
-    __syncthreads();
-    // entries past n are (-inf, max id): they never rank before anything
-    for (uint32_t k = threadIdx.x; k < TILE; k += blockDim.x) {
-      const bool in = t0 + k < n;
-      so[k] = in ? Q.cand_o[t0 + k] : -INFINITY;
-      sid[k] = in ? Q.cand_id[t0 + k] : ~0ull;
-    }
-    __syncthreads();
-    const uint32_t m = (min(TILE, n - t0) + 15u) & ~15u;
-    if (mine) {
-      const float4* so4 = reinterpret_cast<const float4*>(so);
-      for (uint32_t k = 0; k < m; k += 16) {
-        float4 a[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = so4[k / 4 + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float v[4] = {a[u].x, a[u].y, a[u].z, a[u].w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float x = v[e];
-            rank += x > o;
-            if (x == o) rank += sid[k + 4 * u + e] < id;
-          }
-        }
-      }
-    }
-  }
-  if (mine) {
-    out_o[rank] = o;
-    out_id[rank] = id;
-  }
-}
-
 // id -> (reaction, synthon per slot).
 __global__ void k_decode(const ReactDev* __restrict__ react, uint32_t n_react, const uint64_t* __restrict__ ids,
                          const QState* __restrict__ st, uint32_t K, uint32_t* __restrict__ reaction,
@@ -1265,13 +1216,8 @@ hipError_t launch_sort_small(const QueryDev* qs, uint32_t q, uint32_t n_max, uin
 
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
                             uint32_t* rank, hipStream_t s) {
-  if (K <= kSelBracket) {
-    hipError_t e = launch_sort_small(qs, q, K, K, out_o, out_id, rank, s);
-    if (e != hipSuccess) return e;
-  } else {
-    hipLaunchKernelGGL(k_rank_sort, dim3((K + 255) / 256), dim3(256), 0, s, qs, q, out_o, out_id);
-  }
-  return hipGetLastError();
+  if (K > kSelBracket) return hipErrorInvalidValue;  // longer answers are radix-sorted
+  return launch_sort_small(qs, q, K, K, out_o, out_id, rank, s);
 }
 
 hipError_t launch_decode(const ReactDev* react, uint32_t n_react, const uint64_t* ids, const QState* st, uint32_t K,

@@ -36,8 +36,8 @@ hipError_t launch_pool_lookup(const uint64_t* pool_id, const float* pool_heads, 
 hipError_t launch_select(const QueryDev* qs, uint32_t nq, uint32_t chunk_id, int force, hipStream_t s);
 hipError_t launch_tau_relax(const QueryDev* qs, uint32_t nq, hipStream_t s);
 hipError_t launch_state_reset(QState* st, hipStream_t s);
-// Sorts min(count, K) entries of query q by (objective desc, id asc) into out.
-// rank: device scratch of at least min(K, 8192) uint32 (ranks of small sorts).
+// Sorts min(count, K) entries of query q by (objective desc, id asc) into out,
+// K <= 8192 (longer answers take the radix sort). rank: device scratch of K uint32.
 hipError_t launch_rank_sort(const QueryDev* qs, uint32_t q, uint32_t K, float* out_o, uint64_t* out_id,
                             uint32_t* rank, hipStream_t s);
 // Sorts min(count, n_max) <= 8192 entries of query q; the first min(that, n_out)
@@ -63,6 +63,10 @@ hipError_t launch_scan_list(const uint64_t* ids, uint32_t n, const QueryDev* qs,
                             uint32_t n_react, uint64_t n_total, hipStream_t s);
 hipError_t launch_viol_answer(const ScalarQuery* sq, const ReactDev* react, uint32_t n_react, const uint64_t* ids,
                               const QState* st, uint32_t K, float* obj, float* viol, hipStream_t s);
+hipError_t launch_head_quantiles(const float* heads, uint32_t hs, uint32_t n, const float* levels, uint32_t n_levels,
+                                 uint32_t H, float* out, hipStream_t s);
+hipError_t launch_assoc(const AssocSlot* slots, uint32_t n_slots, uint64_t n_tiles, uint32_t d, uint32_t dU,
+                        const float* keys, const float* values, float* out, int n_cu, hipStream_t s);
 hipError_t launch_lin_heads(const float* V, uint32_t hs, const ReactDev* react, uint32_t n_react, uint64_t n_total,
                             const uint64_t* ids, uint32_t n, float* heads, hipStream_t s);
 

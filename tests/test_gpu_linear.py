@@ -196,6 +196,31 @@ def test_linear_keep_violators_warm_start(large):
     _check_keep_violators(lib_h, dec_h, q, r, sample, "keep violators large")
 
 
+def test_head_quantiles_and_counter_screen(large):
+    """Head quantiles over listed compounds equal numpy's linear-interpolation
+    quantiles of the FP64 heads (within FP32 error); a counter-screening query
+    (Appendix A.11: minimise one docking head with the four others above their
+    median, the medians from the engine's own sample) is exact against the
+    oracle."""
+    lib_h, dec_h, (lib, dec, eng), sample = large
+    ids = g.sample_ids(60, "quantile_ids", lib_h.n_compounds, 5000)
+    levels = [0.0, 0.05, 0.5, 0.9, 1.0]
+    print("case: head quantiles", flush=True)
+    got = eng.head_quantiles(levels, ids=ids)
+    h64 = oracle.heads(lib_h, dec_h, ids)
+    want = np.quantile(h64, levels, axis=0)
+    scale = np.sqrt(np.mean(h64 ** 2, axis=0))
+    assert got.shape == (len(levels), H)
+    assert np.all(np.abs(got - want) <= 1e-5 * np.maximum(np.abs(want), scale))
+    med = eng.head_quantiles([0.5], n=8192)[0]
+    assert np.all(np.abs(med - np.median(sample, axis=0)) <= 0.1 * np.std(sample, axis=0))
+    w = np.zeros(H, np.float32)
+    w[0] = -1.0
+    q = Query(w=w, constraints=[Constraint(h, float(med[h]), math.inf) for h in (1, 2, 3, 4)], k=2000)
+    print("case: counter-screen query", flush=True)
+    check_fp32_exact(lib_h, dec_h, q, eng.search(q), "counter-screen")
+
+
 def test_linear_batch_equals_single_and_oracle(small):
     lib_h, dec_h, (lib, dec, eng), sample = small
     qs = [_wide_query(sample, 40), _wide_query(sample, 500, reactions=[1, 3]),

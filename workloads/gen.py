@@ -286,6 +286,16 @@ def make_library(seed: int, n_slots: Sequence[int], slot_sizes: Sequence[int], d
     return Library(n_slots=n_slots, slot_sizes=slot_sizes, d=d, tables=tables)
 
 
+def make_factorizer(seed: int, slot_sizes: Sequence[int], d: int, d_u: int):
+    """Synthetic inputs of the associative embeddings (Section 4.2): one key
+    matrix K_r (d x d_u, entries N(0, 1/d_u)) per R-group and one value vector
+    (d_u, N(0, 1)) per table row. Returns (keys [R, d, d_u], values [rows, d_u])."""
+    n_r, rows = len(slot_sizes), int(np.sum(slot_sizes))
+    keys = (normal_f32(seed, "assoc_keys", n_r * d * d_u) * np.float32(1.0 / math.sqrt(d_u))).reshape(n_r, d, d_u)
+    values = normal_f32(seed, "assoc_values", rows * d_u).reshape(rows, d_u)
+    return keys.astype(np.float32), values
+
+
 def make_decoder(seed: int, dims: Sequence[int], act: int) -> Decoder:
     """Xavier-uniform weights U(+-sqrt(6/(fan_in+fan_out))), biases U(+-1/sqrt(fan_in))."""
     W, b = [], []
