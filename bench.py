@@ -442,14 +442,17 @@ def probe_leg(targets=5, libraries=("12M", "10B", "70B")):
                 eng.profile(True)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
-                found = [len(eng.search(q).ids) for q in qs]
+                res = [eng.search(q) for q in qs]
                 dt = (time.perf_counter() - t1) / len(qs)
+                found = [len(r.ids) for r in res]
                 ms, launches, comps = eng.profile(False)
                 kr = comps / (ms * 1e-3) if ms > 0 else 0.0
                 t4, cpu = PAPER_T4[cons][name][k]
                 entry["runs"].append({
                     "constraints": cons, "k": k, "seconds": dt, "compounds_per_s": n / dt,
                     "kernel_ms": ms / len(qs), "kernel_compounds_per_s": kr, "n_found_min": min(found),
+                    "candidates_mean": float(np.mean([r.n_candidates for r in res])),
+                    "reruns_max": max(r.n_reruns for r in res),
                     "roofline": {"bound": "alu", "achieved": 2 * kr / 1e12, "peak": VALU_PEAK / 1e12,
                                  "unit": "Tops/s", "frac": 2 * kr / VALU_PEAK,
                                  "ops_per_compound": "2 (objective add, threshold compare)",

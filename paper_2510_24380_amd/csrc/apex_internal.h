@@ -21,7 +21,7 @@ constexpr int kTileB = 16;
 // Linear-probe engines (one decoder layer) run the scalar-contribution kernel
 // instead: a tile is 64 "A" rows against 64 "B" rows, one wave, a lane per B
 // row. Such engines have up to kScalarHeads heads.
-constexpr int kScalarTA = 64, kScalarTB = 64;
+constexpr int kScalarTA = 256, kScalarTB = 64;
 constexpr int kScalarHeads = 32;
 
 inline int tile_ta(bool scalar) { return scalar ? kScalarTA : 8; }

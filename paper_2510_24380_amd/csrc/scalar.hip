@@ -110,26 +110,129 @@ __device__ __forceinline__ void wave_append(const QueryDev& Q, bool pass, float 
 }
 
 // ---------------------------------------------------------------------------
-// Enumeration. One wave per tile of 64 A rows x 64 B rows; lane l holds B row
-// b0 + l in a register and takes the tile's A values one at a time from a
+// Enumeration. One wave per tile of kScalarTA A rows x 64 B rows; lane l holds
+// B row b0 + l in a register and takes the tile's A values one at a time from a
 // wave-private LDS row (a broadcast read). Per compound: one add and one max;
 // a group of 16 A rows whose best sum reaches the threshold is re-run with the
-// exact key order, the bounds and the append.
+// exact key order, the bounds and the append. Each wave takes a contiguous run
+// of tiles, so the reaction lookup is a step forward, not a search, and a run
+// of tiles sharing their A rows stages them once (one query per launch).
+// The queries' parameters are copied to LDS once per launch (the threshold
+// does not change during a launch; selections run between launches). In the
+// exact pass the bounds of up to kScanLdsBounds constrained heads are checked
+// from LDS: the tile's B-side values of those heads are staged once (on the
+// tile's first group that reaches the threshold), the group's A-side values per
+// group; queries with more constrained heads read the tables directly.
 // ---------------------------------------------------------------------------
 constexpr int kScanWaves = 4;
 constexpr int kScanGroup = 16;
+constexpr int kScanLdsBounds = 8;
+constexpr uint32_t kScanOut = 128;  // per-wave append buffer (entries)
+
+// Appends gathered in a wave-private LDS buffer and written to the query's
+// candidate buffer with one atomic per flush: the hits of a large-k search are
+// spread thinly over the whole library, and one atomic per hit on the query's
+// single counter would serialise them.
+struct WaveOut {
+  float* o;
+  uint64_t* id;
+  uint32_t n;
+  __device__ void flush(const QueryDev& Q, int lane) {
+    if (n == 0) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&Q.st->count, n);
+    base = __shfl(base, 0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i = (uint32_t)lane; i < n; i += 64) {
+      const uint32_t idx = base + i;
+      if (idx < Q.cap) {
+        Q.cand_o[idx] = o[i];
+        Q.cand_id[idx] = id[i];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    n = 0;
+  }
+  __device__ void append(const QueryDev& Q, bool pass, float ov, uint64_t iv, int lane) {
+    const uint64_t m = __ballot(pass);
+    if (!m) return;
+    const uint32_t c = (uint32_t)__popcll(m);
+    if (n + c > kScanOut) flush(Q, lane);
+    if (pass) {
+      const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+      const uint32_t i = n + (uint32_t)__popcll(m & below);
+      o[i] = ov;
+      id[i] = iv;
+    }
+    n += c;
+  }
+};
+
+struct ScanQ {
+  const ScalarQuery* sq;
+  const float* tab;
+  const uint32_t* bits;
+  float tau_o;
+  uint32_t active;
+  uint64_t tau_id;
+  uint32_t viol;
+  uint32_t n_ch;
+  float lo[kScanLdsBounds];
+  float hi[kScanLdsBounds];
+};
 
 __global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
   __shared__ __attribute__((aligned(16))) float sA[kScanWaves][kScalarTA];
+  __shared__ ScanQ sQ[APEX_MAX_FUSED_QUERIES];
+  __shared__ float sBc[kScanWaves][kScanLdsBounds][64];          // B side of the bounded heads
+  __shared__ float sAc[kScanWaves][kScanLdsBounds][kScanGroup];  // A side, one group
+  __shared__ float sOutO[kScanWaves][kScanOut];
+  __shared__ uint64_t sOutId[kScanWaves][kScanOut];
   const int lane = threadIdx.x & 63, wave = (int)uni32(threadIdx.x >> 6);
-  const uint64_t stride = (uint64_t)gridDim.x * kScanWaves;
+  const uint32_t nq = A.n_queries;
+  if (threadIdx.x < nq) {
+    const QueryDev& Q = A.queries[threadIdx.x];
+    ScanQ L{};
+    L.active = Q.active;
+    if (L.active) {
+      L.sq = Q.sq;
+      L.tab = Q.sq->tab;
+      L.bits = Q.subset_bits;
+      L.tau_o = Q.st->tau_o;
+      L.tau_id = Q.st->tau_id;
+      L.viol = Q.sq->viol;
+      L.n_ch = Q.sq->n_ch;
+      for (int c = 0; c < kScanLdsBounds; ++c) {
+        L.lo[c] = c < (int)L.n_ch ? Q.sq->lo[c] : 0.0f;
+        L.hi[c] = c < (int)L.n_ch ? Q.sq->hi[c] : 0.0f;
+      }
+    }
+    sQ[threadIdx.x] = L;
+  }
+  __syncthreads();
+  // this wave's contiguous run of tiles
+  const uint64_t n_waves = (uint64_t)gridDim.x * kScanWaves;
+  const uint64_t n_tiles = A.tile_end - A.tile_begin;
+  const uint64_t per = (n_tiles + n_waves - 1) / n_waves;
+  uint64_t v = A.tile_begin + ((uint64_t)blockIdx.x * kScanWaves + wave) * per;
+  const uint64_t vend = v + per < A.tile_end ? v + per : A.tile_end;
+  if (v >= vend) return;
   float* row = sA[wave];
-  for (uint64_t v = A.tile_begin + (uint64_t)blockIdx.x * kScanWaves + wave; v < A.tile_end; v += stride) {
-    SelDev S = A.sel[find_sel(A.sel, A.n_sel, v)];
+  WaveOut out{sOutO[wave], sOutId[wave], 0u};
+  uint32_t out_q = 0;  // query whose hits the append buffer holds
+  float (*bc)[64] = sBc[wave];
+  float (*ac)[kScanGroup] = sAc[wave];
+  uint32_t si = uni32(find_sel(A.sel, A.n_sel, v));
+  SelDev S{};
+  ReactDev R{};
+  uint64_t s_end = 0;
+  auto load_reaction = [&]() {
+    S = A.sel[si];
     S.tile_start = uni64(S.tile_start);
     S.t = uni32(S.t);
     S.tiles_b = uni32(S.tiles_b);
-    ReactDev R = A.react[S.t];
+    R = A.react[S.t];
     R.id_off = uni64(R.id_off);
     R.row0 = uni32(R.row0);
     R.row1 = uni32(R.row1);
@@ -138,22 +241,37 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
     R.nA = uni32(R.nA);
     R.nB = uni32(R.nB);
     R.three = uni32(R.three);
+    s_end = S.tile_start + (uint64_t)((R.nA + kScalarTA - 1) / kScalarTA) * S.tiles_b;
+  };
+  load_reaction();
+  uint64_t staged = ~0ull;  // (reaction, A block) whose A values sit in `row` (single query)
+  for (; v < vend; ++v) {
+    while (v >= s_end) {
+      ++si;
+      load_reaction();
+    }
     const uint64_t lt = v - S.tile_start;
     const uint32_t ta = (uint32_t)(lt / S.tiles_b), tb = (uint32_t)(lt - (uint64_t)ta * S.tiles_b);
     const uint32_t a0 = ta * kScalarTA, b = tb * kScalarTB + (uint32_t)lane;
     const uint32_t na = min((uint32_t)kScalarTA, R.nA - a0);
     const bool b_ok = b < R.nB;
-    for (uint32_t qi = 0; qi < A.n_queries; ++qi) {
-      const QueryDev& Q = A.queries[qi];
-      if (!uni32(Q.active)) continue;
-      const uint32_t* bits = uni_ptr(Q.subset_bits);
+    const uint64_t key = ((uint64_t)si << 32) | ta;
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+      const ScanQ& L = sQ[qi];
+      if (!uni32(L.active)) continue;
+      const uint32_t* bits = uni_ptr(L.bits);
       if (bits && !((uni32(bits[S.t >> 5]) >> (S.t & 31)) & 1u)) continue;
-      const ScalarQuery* sq = uni_ptr(Q.sq);
-      const float* col0 = uni_ptr(sq->tab);
-      const float tau_o = unif(Q.st->tau_o);
-      const uint64_t tau_id = uni64(Q.st->tau_id);
+      const ScalarQuery* sq = uni_ptr(L.sq);
+      const float* col0 = uni_ptr(L.tab);
+      const float tau_o = unif(L.tau_o);
+      const uint64_t tau_id = uni64(L.tau_id);
+      const QueryDev& Q = A.queries[qi];
+      if (out_q != qi) {  // the buffer holds one query's hits
+        out.flush(A.queries[out_q], lane);
+        out_q = qi;
+      }
       const float bo = b_ok ? col0[R.rowB + b] : __builtin_nanf("");
-      if (uni32(sq->viol)) {
+      if (uni32(L.viol)) {
         // violation pass: every compound that violates a bound is ranked by its
         // violation (key) against the query's threshold; its objective only
         // needs to be finite
@@ -173,10 +291,20 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
         continue;
       }
       // the row of A values (NaN past the reaction's edge: never passes)
-      __builtin_amdgcn_wave_barrier();
-      row[lane] = (uint32_t)lane < na ? a_value(col0, R, a0 + (uint32_t)lane) : __builtin_nanf("");
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      if (nq > 1 || staged != key) {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < kScalarTA / 64; ++u) {
+          const uint32_t al = (uint32_t)(64 * u + lane);
+          row[al] = al < na ? a_value(col0, R, a0 + al) : __builtin_nanf("");
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        staged = key;
+      }
+      const uint32_t nch = uni32(L.n_ch);
+      const bool lds_bounds = nch <= (uint32_t)kScanLdsBounds;
+      bool bc_staged = false;
       for (uint32_t g = 0; g < na; g += kScanGroup) {
         float mx = -__builtin_inff();
 #pragma unroll
@@ -189,6 +317,23 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
         }
         if (__ballot(mx >= tau_o) == 0) continue;
         const uint32_t ge = min(g + kScanGroup, na);
+        if (nch && lds_bounds) {
+          // the bounded heads' values of this group's A rows (and, once per
+          // tile, of the lane's B row) into LDS
+          __builtin_amdgcn_wave_barrier();
+          const uint64_t rows = sq->rows;
+          if (!bc_staged) {
+            for (uint32_t c = 0; c < nch; ++c)
+              bc[c][lane] = b_ok ? col0[(uint64_t)(c + 1) * rows + R.rowB + b] : __builtin_nanf("");
+            bc_staged = true;
+          }
+          for (uint32_t e = (uint32_t)lane; e < nch * kScanGroup; e += 64) {
+            const uint32_t c = e / kScanGroup, u = e % kScanGroup;
+            ac[c][u] = g + u < na ? a_value(col0 + (uint64_t)(c + 1) * rows, R, a0 + g + u) : __builtin_nanf("");
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
         for (uint32_t al = g; al < ge; ++al) {
           const float o = canon_zero(row[al] + bo);
           bool pass = o >= tau_o;
@@ -196,12 +341,20 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
           const uint32_t a = a0 + al;
           const uint64_t id = R.id_off + (uint64_t)a * R.nB + b;
           pass = pass && finite_obj(o) && key_passes(o, id, tau_o, tau_id);
-          if (pass) pass = scalar_feasible(sq, R, a, b);
-          wave_append(Q, pass, o, id, lane);
+          if (lds_bounds) {
+            for (uint32_t c = 0; c < nch; ++c) {
+              const float hv = ac[c][al - g] + bc[c][lane];
+              pass = pass && hv >= L.lo[c] && hv <= L.hi[c];
+            }
+          } else if (pass) {
+            pass = scalar_feasible(sq, R, a, b);
+          }
+          out.append(Q, pass, o, id, lane);
         }
       }
     }
   }
+  out.flush(A.queries[out_q], lane);
 }
 
 // Listed compounds (the threshold warm start's sample) scored for each query

@@ -49,10 +49,26 @@ uint32_t spec_rank(uint32_t K, uint32_t n_sample, uint64_t n_comp) {
   return r >= (double)K ? K : (uint32_t)r;
 }
 
+// Warm-start sample of the linear path: scoring a sampled compound costs about
+// as much as a few hundred enumerated ones, so the sample grows with the library
+// (1/64 of it, 2^16 .. 2^22 compounds, at least 64 K, at most an eighth of the
+// library): each sampled compound
+// then stands for fewer library compounds and the threshold starts closer to
+// the final K-th key.
+uint64_t scalar_sample(uint32_t K, uint64_t total) {
+  uint64_t s = std::max<uint64_t>(std::max<uint64_t>(64ull * K, total / 64), 1ull << 16);
+  s = std::min<uint64_t>(s, 1ull << 22);
+  // at most an eighth of the library (the warm start's condition), not below 2^16
+  return std::max<uint64_t>(std::min<uint64_t>(s, total / 8), 1ull << 16);
+}
+
 // compounds in the first chunk: small, so that the appends before the first
 // select stay few even with the warm start's loose threshold
 constexpr uint64_t kFirstChunk = 1ull << 20;
 constexpr uint64_t kMaxChunk = 1ull << 27;
+// the scalar-contribution kernel spends ~1e-12 s per compound: its chunks may
+// grow further before a launch and a select per chunk cost more than the chunk
+constexpr uint64_t kMaxChunkScalar = 1ull << 31;
 
 // Test knobs, read from the environment at every search: APEX_TEST_CHUNK fixes
 // the chunk size (compounds) and APEX_TEST_CAP the candidate-buffer capacity
@@ -62,11 +78,12 @@ uint64_t env_u64(const char* name) {
   return v ? strtoull(v, nullptr, 10) : 0;
 }
 
-std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint64_t tile_compounds) {
+std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint64_t tile_compounds, bool scalar) {
   std::vector<std::pair<uint64_t, uint64_t>> out;
   const uint64_t forced = env_u64("APEX_TEST_CHUNK");
   uint64_t per = std::max<uint64_t>(1, (forced ? forced : kFirstChunk) / tile_compounds);
-  const uint64_t max_per = forced ? per : std::max<uint64_t>(1, kMaxChunk / tile_compounds);
+  const uint64_t max_chunk = scalar ? kMaxChunkScalar : kMaxChunk;
+  const uint64_t max_per = forced ? per : std::max<uint64_t>(1, max_chunk / tile_compounds);
   for (uint64_t v = 0; v < n_tiles;) {
     const uint64_t e = std::min(n_tiles, v + per);
     out.emplace_back(v, e);
@@ -150,6 +167,7 @@ void query_sizes(const apex_engine* E, const apex_query* q, QPlan& P) {
   P.K = P.lowp ? pf * P.k : P.k;
   uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(64ull * P.K, 1ull << 18), 1ull << 22);
   cap = std::max<uint64_t>(cap, 2ull * P.K);
+  if (E->scalar) cap = std::max<uint64_t>(cap, scalar_sample(P.K, E->lib->total));
   const uint64_t forced = env_u64("APEX_TEST_CAP");
   if (forced) cap = std::max<uint64_t>(forced, 2ull * P.K);
   P.cap = (uint32_t)cap;
@@ -538,13 +556,14 @@ struct Shared {
   uint32_t n_flags = 0;
 };
 
-uint32_t sample_count(const std::vector<QPlan>& P) {
+uint32_t sample_count(const apex_engine* E, const std::vector<QPlan>& P) {
   uint32_t kmax = 0, capmin = UINT32_MAX;
   for (auto& p : P) {
     kmax = std::max(kmax, p.K);
     capmin = std::min(capmin, p.cap);
   }
-  uint64_t s = std::min<uint64_t>(std::max<uint64_t>(32ull * kmax, 1ull << 16), 1ull << 20);
+  uint64_t s = E->scalar ? scalar_sample(kmax, E->lib->total)
+                         : std::min<uint64_t>(std::max<uint64_t>(32ull * kmax, 1ull << 16), 1ull << 20);
   return (uint32_t)std::min<uint64_t>(s, capmin);
 }
 
@@ -556,14 +575,15 @@ void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& 
     P[i].viol = viol;
   }
   const int prec = (int)qs[0].precision;
-  sh.n_flags = (uint32_t)chunk_schedule(E->prec[prec].full_tiles, tile_compounds(E->scalar)).size() + 1;
-  sh.n_sample = sample_count(P);
+  sh.n_flags = (uint32_t)chunk_schedule(E->prec[prec].full_tiles, tile_compounds(E->scalar), E->scalar).size() + 1;
+  sh.n_sample = sample_count(E, P);
   const uint32_t T = E->lib->T;
   sh.qd = b.take<QueryDev>(n);
   sh.qx = b.take<QueryDev>(n);
   sh.plan = b.take<SelDev>(T);
   sh.sample_ids = b.take<uint64_t>(sh.n_sample);
-  sh.sample_heads = b.take<float>((size_t)sh.n_sample * kHeadsPad);
+  // the linear path scores its sample from the query tables, without heads
+  sh.sample_heads = b.take<float>(E->scalar ? 1 : (size_t)sh.n_sample * kHeadsPad);
   for (uint32_t i = 0; i < n; ++i) query_layout(T, sh.n_flags, b, P[i]);
   for (uint32_t i = 0; i < n; ++i) out_layout(b, P[i]);  // adjacent readback blocks
 }
@@ -653,7 +673,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   }
 
   // 2. chunked enumeration
-  const auto chunks = chunk_schedule(n_tiles, tile_compounds(E->scalar));
+  const auto chunks = chunk_schedule(n_tiles, tile_compounds(E->scalar), E->scalar);
   if (chunks.size() + 1 > sh.n_flags) return set_error(APEX_E_INVALID, "internal: chunk count");
   const uint32_t last_flag = sh.n_flags - 1;  // flag slot of the closing selections (never set)
   for (size_t c = 0; c < chunks.size(); ++c) {

@@ -60,7 +60,8 @@ struct QPlan {
 
 uint64_t env_u64(const char* name);
 uint32_t spec_rank(uint32_t K, uint32_t n_sample, uint64_t n_comp);
-std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint64_t tile_compounds);
+uint64_t scalar_sample(uint32_t K, uint64_t total);
+std::vector<std::pair<uint64_t, uint64_t>> chunk_schedule(uint64_t n_tiles, uint64_t tile_compounds, bool scalar);
 uint32_t tile_compounds(bool scalar);
 apex_status validate_query(const apex_engine* E, const apex_query* q);
 void query_sizes(const apex_engine* E, const apex_query* q, QPlan& P);
