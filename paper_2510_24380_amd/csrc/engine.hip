@@ -335,12 +335,15 @@ extern "C" apex_status apex_engine_workspace_size(const apex_library* lib, const
 }
 
 apex_status apex::engine_gather(apex_engine* E, int prec, const uint64_t* ids, uint32_t n, float* heads,
-                                hipStream_t s) {
+                                hipStream_t s, uint32_t out_stride) {
   if (n == 0) return APEX_OK;
   if (E->scalar) {
-    HIP_TRY(launch_lin_heads(E->P, E->HS, E->react, E->lib->T, E->lib->total, ids, n, heads, s));
+    HIP_TRY(launch_lin_heads(E->P, E->HS, E->react, E->lib->T, E->lib->total, ids, n, heads,
+                             out_stride ? out_stride : E->HS, s));
     return APEX_OK;
   }
+  if (out_stride && out_stride != (uint32_t)kHeadsPad)
+    return set_error(APEX_E_INVALID, "internal: heads stride %u", out_stride);
   const PrecState& S = E->prec[prec];
   EnumArgs a{};
   a.P = E->P;

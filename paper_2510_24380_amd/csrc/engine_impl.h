@@ -107,5 +107,8 @@ namespace apex {
 apex_status set_error(apex_status s, const char* fmt, ...);
 void build_plan(const apex_library* L, bool scalar, const std::vector<uint32_t>& reactions, std::vector<SelDev>& plan,
                 uint64_t* n_tiles, uint64_t* n_compounds);
-apex_status engine_gather(apex_engine* E, int prec, const uint64_t* ids, uint32_t n, float* heads, hipStream_t s);
+// FP32/BF16/FP8 heads of listed compounds, rows of out_stride floats (0: the
+// engine's heads stride; linear-probe engines may write exactly H columns).
+apex_status engine_gather(apex_engine* E, int prec, const uint64_t* ids, uint32_t n, float* heads, hipStream_t s,
+                          uint32_t out_stride = 0);
 }  // namespace apex

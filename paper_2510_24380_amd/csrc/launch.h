@@ -68,7 +68,7 @@ hipError_t launch_head_quantiles(const float* heads, uint32_t hs, uint32_t n, co
 hipError_t launch_assoc(const AssocSlot* slots, uint32_t n_slots, uint64_t n_tiles, uint32_t d, uint32_t dU,
                         const float* keys, const float* values, float* out, int n_cu, hipStream_t s);
 hipError_t launch_lin_heads(const float* V, uint32_t hs, const ReactDev* react, uint32_t n_react, uint64_t n_total,
-                            const uint64_t* ids, uint32_t n, float* heads, hipStream_t s);
+                            const uint64_t* ids, uint32_t n, float* heads, uint32_t ho, hipStream_t s);
 
 // Radix sort (radix_sort.hip) of min(st->count, n_max) entries (src_o, src_id) by
 // (objective desc, id asc); the first min(that, n_out) go to (out_o, out_id).

@@ -412,32 +412,35 @@ __global__ __launch_bounds__(256) void k_viol_answer(const ScalarQuery* __restri
   obj[i] = canon_zero(a_value(sq->tab, R, a) + sq->tab[R.rowB + b]);
 }
 
-// FP32 heads of listed compounds: heads[e * hs + h] for h < hs (zero columns
-// past H); an id past the library's end gives a row of NaN.
+// FP32 heads of listed compounds, one thread per compound: heads[e * ho + h]
+// for h < ho (columns past H are zero); an id past the library's end gives a
+// row of NaN. V has hs >= ho columns.
 __global__ __launch_bounds__(256) void k_lin_heads(const float* __restrict__ V, uint32_t hs,
                                                    const ReactDev* __restrict__ react, uint32_t n_react,
                                                    uint64_t n_total, const uint64_t* __restrict__ ids, uint32_t n,
-                                                   float* __restrict__ heads) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (uint64_t)n * hs) return;
-  const uint32_t e = (uint32_t)(i / hs), h = (uint32_t)(i - (uint64_t)e * hs);
+                                                   float* __restrict__ heads, uint32_t ho) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
   const uint64_t id = ids[e];
-  float x = __builtin_nanf("");
-  if (id < n_total) {
-    const uint32_t t = find_reaction(react, n_react, id);
-    const ReactDev R = react[t];
-    const uint64_t loc = id - R.id_off;
-    const uint32_t a = (uint32_t)(loc / R.nB), b = (uint32_t)(loc - (uint64_t)a * R.nB);
-    float s;
-    if (R.three) {
-      const uint32_t i0 = a / R.n1, i1 = a - i0 * R.n1;
-      s = V[(uint64_t)(R.row0 + i0) * hs + h] + V[(uint64_t)(R.row1 + i1) * hs + h];
-    } else {
-      s = V[(uint64_t)(R.row0 + a) * hs + h];
-    }
-    x = s + V[(uint64_t)(R.rowB + b) * hs + h];
+  float* out = heads + (uint64_t)e * ho;
+  if (id >= n_total) {
+    for (uint32_t h = 0; h < ho; ++h) out[h] = __builtin_nanf("");
+    return;
   }
-  heads[i] = x;
+  const uint32_t t = find_reaction(react, n_react, id);
+  const ReactDev R = react[t];
+  const uint64_t loc = id - R.id_off;
+  const uint32_t a = (uint32_t)(loc / R.nB), b = (uint32_t)(loc - (uint64_t)a * R.nB);
+  const float* vb = V + (uint64_t)(R.rowB + b) * hs;
+  if (R.three) {
+    const uint32_t i0 = a / R.n1, i1 = a - i0 * R.n1;
+    const float* v0 = V + (uint64_t)(R.row0 + i0) * hs;
+    const float* v1 = V + (uint64_t)(R.row1 + i1) * hs;
+    for (uint32_t h = 0; h < ho; ++h) out[h] = (v0[h] + v1[h]) + vb[h];
+  } else {
+    const float* v0 = V + (uint64_t)(R.row0 + a) * hs;
+    for (uint32_t h = 0; h < ho; ++h) out[h] = v0[h] + vb[h];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -480,11 +483,11 @@ hipError_t launch_viol_answer(const ScalarQuery* sq, const ReactDev* react, uint
 }
 
 hipError_t launch_lin_heads(const float* V, uint32_t hs, const ReactDev* react, uint32_t n_react, uint64_t n_total,
-                            const uint64_t* ids, uint32_t n, float* heads, hipStream_t s) {
-  const uint64_t m = (uint64_t)n * hs;
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lin_heads, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, V, hs, react, n_react, n_total,
-                     ids, n, heads);
+                            const uint64_t* ids, uint32_t n, float* heads, uint32_t ho, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (ho == 0 || ho > hs) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lin_heads, dim3((n + 255) / 256), dim3(256), 0, s, V, hs, react, n_react, n_total, ids, n,
+                     heads, ho);
   return hipGetLastError();
 }
 

@@ -154,7 +154,7 @@ static uint32_t constrained_heads(const apex_query* q, uint32_t* head, float* lo
 void query_sizes(const apex_engine* E, const apex_query* q, QPlan& P) {
   P.k = (uint32_t)q->k;
   P.lowp = q->precision != APEX_PREC_FP32;
-  P.hs = E->HS;
+  P.hs = E->scalar ? E->H : E->HS;  // linear-probe answers carry exactly H heads per row
   P.keep = (q->flags & APEX_QUERY_KEEP_VIOLATORS) != 0;
   if (E->scalar) {
     uint32_t head[APEX_MAX_CONSTRAINTS];
@@ -482,7 +482,7 @@ apex_status finish_launch(apex_engine* E, const QPlan& P, const QueryDev* qd_dev
     if (P.viol)  // the sorted keys are violations: move them, recompute the objectives
       HIP_TRY(launch_viol_answer(P.sq, E->react, E->lib->T, P.fin_id, P.st, P.K, P.fin_o, P.fin_c, s));
     // rows past the answer's length are computed from stale ids and never read
-    apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, P.k, P.fin_heads, s);
+    apex_status st = engine_gather(E, APEX_PREC_FP32, P.fin_id, P.k, P.fin_heads, s, P.hs);
     if (st != APEX_OK) return st;
   } else {
     // the pool is the first min(count, K) entries; the scoring ignores the rest
@@ -529,8 +529,12 @@ void finish_read(const apex_engine* E, const QPlan& P, const char* host, const c
   std::memcpy(res->objective, in_copy(host, base, P.fin_o), sizeof(float) * n_found);
   if (res->heads) {
     const float* h = in_copy(host, base, P.fin_heads);
-    for (uint32_t e = 0; e < n_found; ++e)
-      std::memcpy(res->heads + (size_t)e * E->H, h + (size_t)e * P.hs, sizeof(float) * E->H);
+    if (P.hs == E->H) {
+      std::memcpy(res->heads, h, sizeof(float) * E->H * n_found);
+    } else {
+      for (uint32_t e = 0; e < n_found; ++e)
+        std::memcpy(res->heads + (size_t)e * E->H, h + (size_t)e * P.hs, sizeof(float) * E->H);
+    }
   }
   if (res->reaction) std::memcpy(res->reaction, in_copy(host, base, P.fin_reaction), sizeof(uint32_t) * n_found);
   if (res->violation && P.keep) {
