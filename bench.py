@@ -308,6 +308,11 @@ def main_c3(args):
     n = lib.num_compounds
     log(f"engine ready ({n} compounds, {setup_s:.0f} s)")
     flops_c = algorithmic_flops_per_compound(dec_h.dims)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
     for _ in range(args.warmup):
         eng.search(q, precision=args.precision)
         log("warm-up search done")
