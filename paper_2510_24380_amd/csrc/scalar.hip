@@ -20,22 +20,39 @@ namespace apex {
 // ---------------------------------------------------------------------------
 // Per-query row tables.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_qtab(const float* __restrict__ V, uint32_t hs, uint64_t rows, uint32_t H,
+// One thread per row; the row is read as HS / 4 16-byte pieces and the
+// weights come from LDS (the same fma order over heads 0..H-1).
+template <int HS>
+__global__ __launch_bounds__(256) void k_qtab(const float* __restrict__ V, uint64_t rows, uint32_t H,
                                               const ScalarQuery* __restrict__ sq) {
+  __shared__ float w[HS];
+  __shared__ uint32_t head[APEX_MAX_CONSTRAINTS];
+  if (threadIdx.x < HS) w[threadIdx.x] = threadIdx.x < H ? sq->w[threadIdx.x] : 0.0f;
+  if (threadIdx.x < APEX_MAX_CONSTRAINTS) head[threadIdx.x] = sq->head[threadIdx.x];
+  __syncthreads();
   const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  const float* v = V + r * hs;
+  const float4* v4 = reinterpret_cast<const float4*>(V + r * HS);
   float o = 0.0f;
   bool fin = true;
-  for (uint32_t h = 0; h < H; ++h) {
-    const float x = v[h];
-    fin = fin && finite_obj(x);
-    o = fmaf(sq->w[h], x, o);
+#pragma unroll
+  for (int q = 0; q < HS / 4; ++q) {
+    const float4 x = v4[q];
+    const float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t h = 4 * q + e;
+      if (h < H) {
+        fin = fin && finite_obj(xs[e]);
+        o = fmaf(w[h], xs[e], o);
+      }
+    }
   }
   float* tab = sq->tab;
   tab[r] = fin ? o : __builtin_nanf("");
   const uint32_t nch = sq->n_ch;
-  for (uint32_t c = 0; c < nch; ++c) tab[(uint64_t)(c + 1) * rows + r] = v[sq->head[c]];
+  const float* v = V + r * HS;
+  for (uint32_t c = 0; c < nch; ++c) tab[(uint64_t)(c + 1) * rows + r] = v[head[c]];
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +466,13 @@ __global__ __launch_bounds__(256) void k_lin_heads(const float* __restrict__ V, 
 hipError_t launch_qtab(const float* V, uint32_t hs, uint64_t rows, uint32_t H, const ScalarQuery* sq,
                        hipStream_t s) {
   if (rows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_qtab, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, V, hs, rows, H, sq);
+  const dim3 grid((unsigned)((rows + 255) / 256)), block(256);
+  if (hs == 16)
+    hipLaunchKernelGGL(k_qtab<16>, grid, block, 0, s, V, rows, H, sq);
+  else if (hs == 32)
+    hipLaunchKernelGGL(k_qtab<32>, grid, block, 0, s, V, rows, H, sq);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
