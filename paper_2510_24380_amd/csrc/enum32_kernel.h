@@ -29,21 +29,24 @@ namespace apex {
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 template <int PREC> struct Mfma32;
+// mma(a, b, c, sa): c + a b, times 2^(sa - 127) for FP8 (sa: E8M0 scale of
+// the A operand; BF16 has no scale and ignores it).
 template <> struct Mfma32<APEX_PREC_BF16> {
   static constexpr int KS = 16, E = 8, EB = 2;
   using frag = bf16x8;
-  __device__ static inline f32x16 mma(frag a, frag b, f32x16 c) {
+  __device__ static inline f32x16 mma(frag a, frag b, f32x16 c, int) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
 };
 template <> struct Mfma32<APEX_PREC_FP8> {
   static constexpr int KS = 64, E = 32, EB = 1;
   using frag = i32x8;
-  __device__ static inline f32x16 mma(frag a, frag b, f32x16 c) {
-    // E4M3 x E4M3 (format selectors 0); unit scales select the unscaled form.
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+  __device__ static inline f32x16 mma(frag a, frag b, f32x16 c, int sa) {
+    // E4M3 x E4M3 (format selectors 0); E8M0 scales sa on A, 127 (one) on B
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, 127);
   }
 };
+constexpr int kE8M0One = 127;
 
 constexpr int kTileA32 = 8;  // A-rows per tile (2 per wave)
 // Word 3 of a raw buffer resource on gfx9-family parts (32-bit data format;
@@ -99,7 +102,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, j = lane & 31;
   const uint32_t H2 = NL == 2 ? A.H2 : 0;
   const int NC = NL == 2 ? (int)(H2 / 32) : 0;
-  const float S2 = A.pd.scal[0], So = A.pd.scal[1], XS = A.pd.scal[2];
+  const float So = A.pd.scal[1], XS = A.pd.scal[2];
+  // the GEMM's power-of-two scale S2 as an E8M0 exponent (127 + log2 S2)
+  const int s2e = (int)((__float_as_uint(A.pd.scal[0]) >> 23) & 0xffu);
 
   // Work range (XCD-aware contiguous runs, as in the 16x16 kernel).
   uint64_t v, vend;
@@ -306,7 +311,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const Frag wo = load_frag<Frag>(sWo + (size_t)(s * 64 + lane) * E * M::EB);
-        hacc = M::mma(wo, X[s], hacc);
+        hacc = M::mma(wo, X[s], hacc, kE8M0One);
       }
     } else {
       // The staged rows are no longer needed: the region takes the weight chunks.
@@ -377,14 +382,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           if (s + 2 < NS) ring[(s + 2) % 3] = load_frag<Frag>(wc + (size_t)((s + 2) * 64 + lane) * E * M::EB);
-          acc = M::mma(ring[s % 3], X[s], acc);
+          acc = M::mma(ring[s % 3], X[s], acc, s2e);
           if (fin) {
             // the operations of act_pre, one at a time (same arithmetic)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
               if (fstep(v, 0) == s) {
                 float u = old[v];
-                if (PREC == APEX_PREC_FP8) u *= S2;
                 if constexpr (ACT == APEX_ACT_SILU) {
                   y[v] = u;
                   tq[v] = __builtin_amdgcn_exp2f(u);
@@ -421,7 +425,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             float u = acc[8 * st + e];
-            if (PREC == APEX_PREC_FP8) u *= S2;
             xb[e] = (__bf16)act_pre<ACT>(u);
           }
           hacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wo, xb, hacc, 0, 0, 0);

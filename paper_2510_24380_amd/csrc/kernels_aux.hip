@@ -116,15 +116,25 @@ __global__ void k_absmax(const float* __restrict__ x, uint64_t n, float* __restr
   if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
 }
 
+// Power-of-two scale 2^ceil(log2(m / 448)) that maps [0, m] into the E4M3
+// range, clamped to [2^-60, 2^60] (1 for an empty or non-finite range).
+__device__ inline float pow2_scale(float m) {
+  if (!(m > 0.0f) || !(m < __builtin_inff())) return 1.0f;
+  return exp2f(fminf(fmaxf(ceilf(log2f(m / 448.0f)), -60.0f), 60.0f));
+}
+
 // Scales of one precision. amax: [0] activation range, [1] |W2|, [2] |Wo|.
 // scal: [0] S2, [1] So, [2] X conversion scale, [3] 1/s_w2, [4] 1/s_wo.
+// The activation and W2 scales are powers of two, so S2 = s_w2 * xs is one
+// too and the FP8 GEMM applies it as the MFMA's E8M0 scale of its weight
+// operand (E4M3 rounding is relative, so a power-of-two scale loses nothing
+// but the top of the range: the largest weight maps into (224, 448]).
 __global__ void k_scales(const float* __restrict__ amax, int prec, int nl, float* __restrict__ scal) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   float S2 = 1.0f, So = 1.0f, xs = 1.0f, iw2 = 1.0f, iwo = 1.0f;
   if (prec == APEX_PREC_FP8) {
-    const float ax = amax[0] > 0.0f ? amax[0] : 1.0f;
-    xs = exp2f(ceilf(log2f(ax / 448.0f)));
-    const float sw2 = amax[1] > 0.0f ? amax[1] / 448.0f : 1.0f;
+    xs = pow2_scale(amax[0]);
+    const float sw2 = pow2_scale(amax[1]);
     const float swo = amax[2] > 0.0f ? amax[2] / 448.0f : 1.0f;
     iw2 = 1.0f / sw2;
     iwo = 1.0f / swo;
@@ -216,13 +226,13 @@ __global__ void k_frag_out32(const float* __restrict__ Wo, uint32_t H, uint32_t 
   }
 }
 
-// GEMM accumulator start values c * b2 / S2 (zero for padding neurons h2 ..
-// h2k - 1), and the padded final bias.
+// GEMM accumulator start values c * b2 (zero for padding neurons h2 .. h2k - 1;
+// the GEMM's scale S2 multiplies only the product), and the padded final bias.
 __global__ void k_bias(const float* __restrict__ b2, uint32_t h2, uint32_t h2k, float c, const float* __restrict__ scal,
                        const float* __restrict__ bo, uint32_t H, float* __restrict__ b2_out,
                        float* __restrict__ bo_out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b2 && i < h2k) b2_out[i] = i < h2 ? c * b2[i] / scal[0] : 0.0f;
+  if (b2 && i < h2k) b2_out[i] = i < h2 ? c * b2[i] : 0.0f;
   if (i < kHeadsPad) bo_out[i] = i < H ? bo[i] : 0.0f;
 }
 

@@ -42,6 +42,13 @@ __global__ void k_fp8_32(const i32x8* a, const i32x8* b, float* d) {
   c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[l], b[l], c, 0, 0, 0, 0, 0, 0);
   for (int v = 0; v < 16; ++v) d[16 * l + v] = c[v];
 }
+// the same with E8M0 block scales sa, sb (2^(sa - 127), 2^(sb - 127)) on A and B
+__global__ void k_fp8_32s(const i32x8* a, const i32x8* b, float* d, int sa, int sb) {
+  const int l = threadIdx.x;
+  f32x16 c = {};
+  c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[l], b[l], c, 0, 0, 0, sa, 0, sb);
+  for (int v = 0; v < 16; ++v) d[16 * l + v] = c[v];
+}
 // x[i] -> E4M3 byte with power-of-two scale xs (divides), and -> bf16 bits
 __global__ void k_cvt(const float* x, int n, float xs, uint8_t* f8, uint16_t* bf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,6 +69,11 @@ extern "C" int probe_mfma(int kind, const void* a, const void* b, float* d) {
   else if (kind == 3) hipLaunchKernelGGL(k_bf16_32, dim3(1), dim3(64), 0, 0, (const bf16x8*)a, (const bf16x8*)b, d);
   else if (kind == 4) hipLaunchKernelGGL(k_fp8_32, dim3(1), dim3(64), 0, 0, (const i32x8*)a, (const i32x8*)b, d);
   else return -1;
+  return (int)hipDeviceSynchronize();
+}
+extern "C" int probe_mfma_fp8_scaled(const void* a, const void* b, float* d, int sa, int sb) {
+  if (sa < 0 || sa > 254 || sb < 0 || sb > 254) return -1;
+  hipLaunchKernelGGL(k_fp8_32s, dim3(1), dim3(64), 0, 0, (const i32x8*)a, (const i32x8*)b, d, sa, sb);
   return (int)hipDeviceSynchronize();
 }
 extern "C" int probe_cvt(const float* x, int n, float xs, uint8_t* f8, uint16_t* bf) {

@@ -34,6 +34,7 @@ def probe():
     lib = ctypes.CDLL(SO)
     lib.probe_mfma.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.probe_cvt.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]
+    lib.probe_mfma_fp8_scaled.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     return lib
 
 
@@ -133,6 +134,33 @@ def test_mfma_fp8_32x32x64(probe):
     e_norm = float(np.max(np.abs(D - A @ B) / (np.abs(A) @ np.abs(B))))
     print(f"fp8 32x32x64 mfma, normal inputs: max error / sum|ab| {e_norm:.2e}")
     assert e_norm < 2e-3
+
+
+def test_mfma_fp8_32x32x64_block_scales(probe):
+    """The scaled form multiplies the product by 2^(sa - 127) 2^(sb - 127) (E8M0
+    scales), exactly: the FP8 kernel applies the GEMM's power-of-two scale this
+    way instead of one multiply per activation."""
+    rng = np.random.default_rng(7)
+    tab = e4m3_table()
+    okn = np.where(np.isfinite(tab) & (np.abs(tab) <= 8) & (np.abs(tab) >= 2.0 ** -6))[0]
+    ca = rng.choice(okn, (32, 64)).astype(np.uint8)
+    cb = rng.choice(okn, (64, 32)).astype(np.uint8)
+    a = np.zeros((64, 32), np.uint8)
+    b = np.zeros((64, 32), np.uint8)
+    for l in range(64):
+        for e in range(32):
+            k = 32 * (l // 32) + e
+            a[l, e] = ca[l % 32, k]
+            b[l, e] = cb[k, l % 32]
+    D, regs = run32(probe, 4, a, b)
+    for sa, sb in [(127, 127), (130, 127), (127 - 9, 127), (131, 127 - 6)]:
+        at = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+        d = torch.zeros(64 * 16, dtype=torch.float32, device="cuda")
+        assert probe.probe_mfma_fp8_scaled(at.data_ptr(), bt.data_ptr(), d.data_ptr(), sa, sb) == 0
+        got = d.cpu().numpy().reshape(64, 16)
+        want = (regs.astype(np.float64) * 2.0 ** (sa - 127 + sb - 127)).astype(np.float32)
+        assert np.array_equal(got, want), f"scales {sa}, {sb}"
 
 
 def test_mfma_fp8_16x16x128(probe):
