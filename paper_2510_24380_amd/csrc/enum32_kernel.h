@@ -31,16 +31,27 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 template <int PREC> struct Mfma32;
 // mma(a, b, c, sa): c + a b, times 2^(sa - 127) for FP8 (sa: E8M0 scale of
 // the A operand; BF16 has no scale and ignores it).
+// frag(base, s, lane): the lane's weight fragment of k-step s of a chunk in LDS
+// (k-step blocks of 64 lanes x 16 bytes; FP8 keeps a lane's two halves in two
+// consecutive blocks).
 template <> struct Mfma32<APEX_PREC_BF16> {
   static constexpr int KS = 16, E = 8, EB = 2;
   using frag = bf16x8;
   __device__ static inline f32x16 mma(frag a, frag b, f32x16 c, int) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
+  __device__ static inline frag frag_at(const unsigned char* base, int s, int lane) {
+    return *reinterpret_cast<const frag*>(base + (size_t)(s * 64 + lane) * 16);
+  }
 };
 template <> struct Mfma32<APEX_PREC_FP8> {
   static constexpr int KS = 64, E = 32, EB = 1;
   using frag = i32x8;
+  __device__ static inline frag frag_at(const unsigned char* base, int s, int lane) {
+    const int4 lo = *reinterpret_cast<const int4*>(base + (size_t)s * 2048 + lane * 16);
+    const int4 hi = *reinterpret_cast<const int4*>(base + (size_t)s * 2048 + 1024 + lane * 16);
+    return frag{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  }
   __device__ static inline f32x16 mma(frag a, frag b, f32x16 c, int sa) {
     // E4M3 x E4M3 (format selectors 0); E8M0 scales sa on A, 127 (one) on B
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, 127);
@@ -310,7 +321,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if constexpr (NL == 1) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const Frag wo = load_frag<Frag>(sWo + (size_t)(s * 64 + lane) * E * M::EB);
+        const Frag wo = M::frag_at(sWo, s, lane);
         hacc = M::mma(wo, X[s], hacc, kE8M0One);
       }
     } else {
@@ -375,13 +386,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         if (pf) load_chunk(c + 1, (c + 1) & 1);
         const unsigned char* wc = sW + (c & 1) * CHUNK;
         Frag ring[3];
-        ring[0] = load_frag<Frag>(wc + (size_t)lane * E * M::EB);
-        if (NS > 1) ring[1] = load_frag<Frag>(wc + (size_t)(64 + lane) * E * M::EB);
+        ring[0] = M::frag_at(wc, 0, lane);
+        if (NS > 1) ring[1] = M::frag_at(wc, 1, lane);
         float y[16], tq[16];
         bf16x8 xb[2];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          if (s + 2 < NS) ring[(s + 2) % 3] = load_frag<Frag>(wc + (size_t)((s + 2) * 64 + lane) * E * M::EB);
+          if (s + 2 < NS) ring[(s + 2) % 3] = M::frag_at(wc, s + 2, lane);
           acc = M::mma(ring[s % 3], X[s], acc, s2e);
           if (fin) {
             // the operations of act_pre, one at a time (same arithmetic)

@@ -191,7 +191,10 @@ template <> __device__ inline void store_elem<APEX_PREC_FP8>(void* base, uint64_
 
 // Operand fragments for the 32x32 kernel (BF16, FP8): A fragment (c, s, lane, e)
 // holds W[32 c + lane % 32][h n_in/2 + s E + e] * mul, h = lane / 32 (rows at or
-// beyond n_out are zero).
+// beyond n_out are zero). Each k-step of a chunk is 64 lanes x 16 bytes per
+// 1 KB block: BF16 (E = 8) fills one block, lane-major; FP8 (E = 32 bytes per
+// lane) fills two, elements 0..15 of every lane, then 16..31, so each of a
+// lane's two 16-byte LDS reads covers 1 KB contiguously (no bank conflicts).
 template <int PREC>
 __global__ void k_frag_x32(const float* __restrict__ W, uint32_t n_out, uint32_t n_in, uint32_t n_chunks,
                            const float* __restrict__ mul_dev, float mul, void* __restrict__ out) {
@@ -200,8 +203,8 @@ __global__ void k_frag_x32(const float* __restrict__ W, uint32_t n_out, uint32_t
   const uint64_t total = (uint64_t)n_chunks * ns * 64 * E;
   const float m = mul * (mul_dev ? *mul_dev : 1.0f);
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t e = i % E;
-    const uint32_t lane = (i / E) % 64;
+    const uint32_t e = PREC == APEX_PREC_BF16 ? i % E : (i % 16) + 16 * ((i / 1024) % 2);
+    const uint32_t lane = PREC == APEX_PREC_BF16 ? (i / E) % 64 : (i / 16) % 64;
     const uint32_t s = (i / ((uint64_t)E * 64)) % ns;
     const uint32_t c = (uint32_t)(i / ((uint64_t)E * 64 * ns));
     const uint32_t row = 32 * c + lane % 32;
