@@ -105,24 +105,32 @@ def profile_values(name, prec, workload="c1"):
 
 
 def valu_estimate(prec, flops_per_compound, compounds_per_launch, avg_launch_ms):
-    """Vector-ALU time of one launch beside its MFMA time, from the committed
-    issue-level counters: lane operations / (256 CUs x 64 lanes x 2.4 GHz), with
-    transcendentals counted once (full rate) and four times (quarter rate)."""
+    """Issue time of one launch's vector work beside its MFMA time, from the
+    committed issue-level counters and the per-SIMD issue costs measured by
+    throughput probes on gfx950: 4 cycles per VALU wave instruction, 8 per
+    transcendental (exp2, rcp: half rate), and 8 cycles of VALU issue taken by
+    each 32x32 MFMA (a VALU-only wave beside a saturated MFMA chain loses a
+    quarter of its rate; measured for the BF16 shape, assumed for FP8). The
+    1024 SIMDs issue at 2.4 GHz, the clock the peaks are quoted at."""
     v = profile_values("sq_counters", prec)
-    if v is None:
+    if v is None or "mfma_insts_per_compound" not in v:
         return None
-    lanes_per_s = 256 * 64 * 2.4e9
-    insts = float(v["valu_insts_per_compound"])
+    simd_hz = 1024 * 2.4e9
+    insts = float(v["valu_insts_per_compound"])  # MFMA included
     trans = float(v["trans_insts_per_compound"])
-    t_full = insts * 64 * compounds_per_launch / lanes_per_s
-    t_quarter = (insts + 3 * trans) * 64 * compounds_per_launch / lanes_per_s
+    mfma = float(v["mfma_insts_per_compound"])
+    cycles = 4 * (insts - trans - mfma) + 8 * trans + 8 * mfma
+    t_issue = cycles * compounds_per_launch / simd_hz
     t_mfma = flops_per_compound * compounds_per_launch / PEAK[prec]
-    return {"valu_insts_per_compound": insts, "trans_insts_per_compound": trans,
-            "t_valu_ms_full_rate": t_full * 1e3, "t_valu_ms_trans_quarter_rate": t_quarter * 1e3,
-            "t_mfma_ms_at_peak": t_mfma * 1e3, "t_launch_ms": avg_launch_ms,
-            "valu_bound_at_peak": t_quarter > t_mfma,
+    clock = float(v["clock_ghz_under_load"])
+    return {"valu_insts_per_compound": insts, "trans_insts_per_compound": trans, "mfma_insts_per_compound": mfma,
+            "issue_cycles_per_compound": cycles,
+            "issue_model": "4 cycles per VALU instruction, 8 per transcendental, 8 per 32x32 MFMA (per SIMD)",
+            "t_issue_ms": t_issue * 1e3, "t_mfma_ms_at_peak": t_mfma * 1e3, "t_launch_ms": avg_launch_ms,
+            "issue_bound_at_peak": t_issue > t_mfma,
+            "issue_frac_at_measured_clock": t_issue * 2.4 / clock / (avg_launch_ms * 1e-3) if avg_launch_ms else None,
             "measured_mfma_busy": float(v["mfma_busy"]), "measured_valu_active": float(v["valu_active"]),
-            "measured_clock_ghz": float(v["clock_ghz_under_load"])}
+            "measured_clock_ghz": clock}
 
 
 def algorithmic_flops_per_compound(dims):
