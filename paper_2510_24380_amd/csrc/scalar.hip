@@ -377,13 +377,44 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_scan(EnumArgs A) {
 // Listed compounds (the threshold warm start's sample) scored for each query
 // with the enumeration's arithmetic and appended if they pass; ids past the
 // library's end are skipped.
-__global__ __launch_bounds__(256) void k_scan_list(const uint64_t* __restrict__ ids, uint32_t n,
+// Append of a whole workgroup (every thread calls it once): one atomic on the
+// query's counter per workgroup instead of one per wave. The warm-start sample
+// is scored against an open threshold, so every listed compound appends, and
+// per-wave atomics on the one counter serialise.
+constexpr int kListThreads = 1024;
+__device__ __forceinline__ void block_append(const QueryDev& Q, bool pass, float o, uint64_t id) {
+  __shared__ uint32_t s_off[kListThreads / 64];
+  __shared__ uint32_t s_base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t m = __ballot(pass);
+  if (lane == 0) s_off[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t total = 0;
+    for (int w = 0; w < kListThreads / 64; ++w) {
+      const uint32_t c = s_off[w];
+      s_off[w] = total;
+      total += c;
+    }
+    s_base = total ? atomicAdd(&Q.st->count, total) : 0u;
+  }
+  __syncthreads();
+  if (pass) {
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t idx = s_base + s_off[wave] + (uint32_t)__popcll(m & below);
+    if (idx < Q.cap) {
+      Q.cand_o[idx] = o;
+      Q.cand_id[idx] = id;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kListThreads) void k_scan_list(const uint64_t* __restrict__ ids, uint32_t n,
                                                    const QueryDev* __restrict__ qs, uint32_t nq,
                                                    const ReactDev* __restrict__ react, uint32_t n_react,
                                                    uint64_t n_total) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t q = blockIdx.y;
-  const int lane = threadIdx.x & 63;
   if (q >= nq) return;  // uniform per workgroup
   const QueryDev& Q = qs[q];
   if (!Q.active) return;
@@ -408,7 +439,7 @@ __global__ __launch_bounds__(256) void k_scan_list(const uint64_t* __restrict__ 
       }
     }
   }
-  wave_append(Q, pass, o, id, lane);
+  block_append(Q, pass, o, id);  // every thread of the workgroup
 }
 
 // Answer of a violation pass: the sorted keys (violations) move to viol, and
@@ -493,8 +524,8 @@ hipError_t launch_scan(const EnumArgs& a, uint32_t grid_max, hipStream_t s) {
 hipError_t launch_scan_list(const uint64_t* ids, uint32_t n, const QueryDev* qs, uint32_t nq, const ReactDev* react,
                             uint32_t n_react, uint64_t n_total, hipStream_t s) {
   if (n == 0 || nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_list, dim3((n + 255) / 256, nq), dim3(256), 0, s, ids, n, qs, nq, react, n_react,
-                     n_total);
+  hipLaunchKernelGGL(k_scan_list, dim3((n + kListThreads - 1) / kListThreads, nq), dim3(kListThreads), 0, s, ids, n,
+                     qs, nq, react, n_react, n_total);
   return hipGetLastError();
 }
 
