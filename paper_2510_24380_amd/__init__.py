@@ -7,6 +7,7 @@ from .binding import (  # noqa: F401
     Decoder,
     Engine,
     Library,
+    ResultBuffers,
     SearchResult,
     Server,
     lib,

@@ -250,14 +250,46 @@ class _QueryMarshal:
                         self.subset.ctypes.data if subset is not None else None, flags)
 
 
+class ResultBuffers:
+    """Result arrays for answers of up to `capacity` entries, in pinned host
+    memory, for reuse across searches (`Engine.search(..., out=buffers)`): the
+    library copies long answers into them straight from the device, and no
+    fresh host memory is touched per search. A result returned through them
+    views these arrays and is overwritten by the next search that uses them."""
+
+    def __init__(self, capacity: int, n_heads: int):
+        def pinned(shape, dtype):
+            return torch.empty(shape, dtype=dtype, pin_memory=True)
+        self.capacity = int(capacity)
+        self.n_heads = int(n_heads)
+        # torch has no unsigned 64/32-bit dtypes for pinned tensors: int64/int32
+        # storage viewed as uint64/uint32
+        self._t = [pinned((capacity,), torch.int64), pinned((capacity,), torch.float32),
+                   pinned((capacity, n_heads), torch.float32), pinned((capacity,), torch.int32),
+                   pinned((capacity, 3), torch.int32), pinned((capacity,), torch.float32)]
+        self.ids = self._t[0].numpy().view(np.uint64)
+        self.obj = self._t[1].numpy()
+        self.heads = self._t[2].numpy()
+        self.reaction = self._t[3].numpy().view(np.uint32)
+        self.synthon = self._t[4].numpy().view(np.uint32)
+        self.viol = self._t[5].numpy()
+
+
 class _ResultMarshal:
-    def __init__(self, k: int, n_heads: int):
-        self.ids = np.empty(k, np.uint64)
-        self.obj = np.empty(k, np.float32)
-        self.heads = np.empty((k, n_heads), np.float32)
-        self.reaction = np.empty(k, np.uint32)
-        self.synthon = np.empty((k, 3), np.uint32)
-        self.viol = np.empty(k, np.float32)
+    def __init__(self, k: int, n_heads: int, out: Optional[ResultBuffers] = None):
+        if out is not None:
+            if out.capacity < k or out.n_heads != n_heads:
+                raise ValueError(f"result buffers hold {out.capacity} x {out.n_heads} heads, "
+                                 f"the query needs {k} x {n_heads}")
+            self.ids, self.obj, self.heads = out.ids, out.obj, out.heads
+            self.reaction, self.synthon, self.viol = out.reaction, out.synthon, out.viol
+        else:
+            self.ids = np.empty(k, np.uint64)
+            self.obj = np.empty(k, np.float32)
+            self.heads = np.empty((k, n_heads), np.float32)
+            self.reaction = np.empty(k, np.uint32)
+            self.synthon = np.empty((k, 3), np.uint32)
+            self.viol = np.empty(k, np.float32)
         self.c = ResultC(k, self.ids.ctypes.data, self.obj.ctypes.data, self.heads.ctypes.data,
                          self.reaction.ctypes.data, self.synthon.ctypes.data, 0, 0, 0, 0, self.viol.ctypes.data)
 
@@ -300,17 +332,20 @@ class Engine:
         return int(n.value)
 
     def search(self, q, precision: str = "fp32", pool_factor: int = 0,
-               stream: Optional[torch.cuda.Stream] = None) -> SearchResult:
-        return self.search_batch([q], precision, pool_factor, stream)[0]
+               stream: Optional[torch.cuda.Stream] = None, out: Optional[ResultBuffers] = None) -> SearchResult:
+        """One query. With `out`, the result views those reusable pinned arrays
+        (see ResultBuffers); otherwise it owns freshly allocated ones."""
+        return self.search_batch([q], precision, pool_factor, stream, outs=None if out is None else [out])[0]
 
     def search_batch(self, qs, precision: str = "fp32", pool_factor: int = 0,
-                     stream: Optional[torch.cuda.Stream] = None) -> List[SearchResult]:
+                     stream: Optional[torch.cuda.Stream] = None,
+                     outs: Optional[List[ResultBuffers]] = None) -> List[SearchResult]:
         ms = [_QueryMarshal(q, self.n_heads, precision, pool_factor) for q in qs]
         arr = (QueryC * len(ms))(*[m.c for m in ms])
         n = ctypes.c_size_t()
         _check(lib().apex_batch_workspace_size(self.handle, arr, len(ms), ctypes.byref(n)))
         ws = self._workspace(int(n.value))
-        rs = [_ResultMarshal(int(q.k), self.n_heads) for q in qs]
+        rs = [_ResultMarshal(int(q.k), self.n_heads, None if outs is None else outs[i]) for i, q in enumerate(qs)]
         rarr = (ResultC * len(rs))(*[r.c for r in rs])
         if len(ms) == 1:
             st = lib().apex_search(self.handle, arr, ws.data_ptr(), ws.numel(), _stream_ptr(stream), rarr)

@@ -65,6 +65,9 @@ uint64_t scalar_sample(uint32_t K, uint64_t total) {
 // compounds in the first chunk: small, so that the appends before the first
 // select stay few even with the warm start's loose threshold
 constexpr uint64_t kFirstChunk = 1ull << 20;
+// answer arrays longer than this are copied from the device straight into the
+// result arrays instead of through the readback of the whole output block
+constexpr size_t kDirectReadback = 4u << 20;
 constexpr uint64_t kMaxChunk = 1ull << 27;
 // the scalar-contribution kernel spends ~1e-12 s per compound: its chunks may
 // grow further before a launch and a select per chunk cost more than the chunk
@@ -546,6 +549,35 @@ void finish_read(const apex_engine* E, const QPlan& P, const char* host, const c
   if (res->synthon) std::memcpy(res->synthon, in_copy(host, base, P.fin_synthon), sizeof(uint32_t) * 3 * n_found);
 }
 
+apex_status finish_read_direct(const apex_engine* E, const QPlan& P, const char* host, const char* base,
+                               apex_result* res, hipStream_t s) {
+  const QState st1 = *in_copy(host, base, P.st);
+  const uint32_t n1 = std::min(st1.count, P.K);
+  const uint32_t n_found = P.lowp ? std::min(in_copy(host, base, P.st2)->count, P.k) : n1;
+  res->n_found = n_found;
+  res->n_candidates = st1.appended;
+  if (n_found == 0) return APEX_OK;
+  const auto d2h = hipMemcpyDeviceToHost;
+  HIP_TRY(hipMemcpyAsync(res->ids, P.fin_id, sizeof(uint64_t) * n_found, d2h, s));
+  HIP_TRY(hipMemcpyAsync(res->objective, P.fin_o, sizeof(float) * n_found, d2h, s));
+  if (res->heads) {
+    if (P.hs == E->H)
+      HIP_TRY(hipMemcpyAsync(res->heads, P.fin_heads, sizeof(float) * E->H * n_found, d2h, s));
+    else
+      HIP_TRY(hipMemcpy2DAsync(res->heads, sizeof(float) * E->H, P.fin_heads, sizeof(float) * P.hs,
+                               sizeof(float) * E->H, n_found, d2h, s));
+  }
+  if (res->reaction) HIP_TRY(hipMemcpyAsync(res->reaction, P.fin_reaction, sizeof(uint32_t) * n_found, d2h, s));
+  if (res->violation && P.keep) {
+    if (P.viol)
+      HIP_TRY(hipMemcpyAsync(res->violation, P.fin_c, sizeof(float) * n_found, d2h, s));
+    else
+      std::fill(res->violation, res->violation + n_found, 0.0f);
+  }
+  if (res->synthon) HIP_TRY(hipMemcpyAsync(res->synthon, P.fin_synthon, sizeof(uint32_t) * 3 * n_found, d2h, s));
+  return APEX_OK;
+}
+
 }  // namespace apex
 
 namespace {
@@ -694,18 +726,36 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   // which case those chunks are re-run and the answers enqueued again
   const char* base = P[0].out;
   const size_t span = (size_t)((P[nq - 1].out + P[nq - 1].out_bytes) - base);
-  Readback rb(E, span, pageable_readback);
+  // Long answers (over kDirectReadback bytes): each round reads back only the
+  // queries' control words, and the answer arrays go from the device straight
+  // into the result arrays once the rounds settle, n_found entries each.
+  std::vector<size_t> ctl_off(nq);
+  size_t ctl_total = 0;
+  for (uint32_t i = 0; i < nq; ++i) {
+    ctl_off[i] = ctl_total;
+    ctl_total += out_control_bytes(P[i]);
+  }
+  const bool direct = span - ctl_total > kDirectReadback;
+  Readback rb(E, direct ? ctl_total : span, pageable_readback);
+  auto host_of = [&](uint32_t i) -> const char* {  // host copy of query i's block from P[i].out on
+    return direct ? rb.data() + ctl_off[i] : rb.data() + (P[i].out - base);
+  };
   uint32_t reruns = 0;
   for (int round = 0;; ++round) {
     for (uint32_t i = 0; i < nq; ++i) {
       apex_status st = finish_launch(E, P[i], sh.qd + i, sh.qx + i, s);
       if (st != APEX_OK) return st;
     }
-    HIP_TRY(hipMemcpyAsync(rb.data(), base, span, hipMemcpyDeviceToHost, s));
+    if (direct) {
+      for (uint32_t i = 0; i < nq; ++i)
+        HIP_TRY(hipMemcpyAsync(rb.data() + ctl_off[i], P[i].out, out_control_bytes(P[i]), hipMemcpyDeviceToHost, s));
+    } else {
+      HIP_TRY(hipMemcpyAsync(rb.data(), base, span, hipMemcpyDeviceToHost, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     std::vector<uint32_t> flags((size_t)nq * sh.n_flags);
     for (uint32_t i = 0; i < nq; ++i)
-      std::memcpy(flags.data() + (size_t)i * sh.n_flags, out_flags(P[i], rb.data(), base), 4 * sh.n_flags);
+      std::memcpy(flags.data() + (size_t)i * sh.n_flags, out_flags(P[i], host_of(i), P[i].out), 4 * sh.n_flags);
     // a speculative threshold that left fewer than K survivors was above the
     // final K-th key: that query is enumerated again from scratch
     std::vector<uint8_t> redo(nq, 0);
@@ -713,7 +763,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
     for (uint32_t i = 0; i < nq; ++i) {
       if (!spec[i]) continue;
       spec[i] = 0;
-      const QState* st = reinterpret_cast<const QState*>(rb.data() + ((const char*)P[i].st - base));
+      const QState* st = in_copy(host_of(i), P[i].out, P[i].st);
       if (st->warm && st->count < P[i].K) {
         redo[i] = 1;
         any_redo = true;
@@ -765,10 +815,16 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
     HIP_TRY(launch_select(sh.qd, nq, last_flag, 1, s));
   }
   for (uint32_t i = 0; i < nq; ++i) {
-    finish_read(E, P[i], rb.data(), base, &res[i]);
+    if (direct) {
+      apex_status st = finish_read_direct(E, P[i], host_of(i), P[i].out, &res[i], s);
+      if (st != APEX_OK) return st;
+    } else {
+      finish_read(E, P[i], host_of(i), P[i].out, &res[i]);
+    }
     res[i].n_scored = scored;
     res[i].n_reruns = reruns;
   }
+  if (direct) HIP_TRY(hipStreamSynchronize(s));
   return profile_collect(E);
 }
 

@@ -98,6 +98,13 @@ const uint32_t* out_flags(const QPlan& P, const char* host, const char* base);
 // Fills res (n_found, n_candidates and the requested arrays) from a host copy of
 // readback blocks that starts at block `base`.
 void finish_read(const apex_engine* E, const QPlan& P, const char* host, const char* base, apex_result* res);
+// The same from the device: the counts from the host copy of the query's
+// control words, the answer arrays (n_found entries) copied on stream s
+// straight into the result arrays (a DMA when they are pinned host memory).
+apex_status finish_read_direct(const apex_engine* E, const QPlan& P, const char* host, const char* base,
+                               apex_result* res, hipStream_t s);
+// Bytes of a query's output block before its answer arrays (states and re-run flags).
+inline size_t out_control_bytes(const QPlan& P) { return (size_t)((const char*)P.fin_o - P.out); }
 
 // A pinned host buffer from the engine's pool (ordinary host memory if pinning
 // fails), returned to the pool on destruction. With pageable = true it is

@@ -44,6 +44,30 @@ def test_probe_12m_long_answers(probe12m, k):
     check_fp32_exact(lib_h, dec_h, q, r, f"probe 12M k={k}")
 
 
+def _same_result(a, b, label):
+    assert np.array_equal(a.ids, b.ids), label
+    assert np.array_equal(a.objective.view(np.uint32), b.objective.view(np.uint32)), label
+    assert np.array_equal(a.heads.view(np.uint32), b.heads.view(np.uint32)), label
+    assert np.array_equal(a.reaction, b.reaction) and np.array_equal(a.synthon, b.synthon), label
+
+
+def test_probe_12m_pinned_result_buffers(probe12m):
+    """Long answers through reusable pinned result arrays (copied straight from
+    the device) equal the ones in fresh arrays, for two searches in a row into
+    the same arrays, the second with the longer answer."""
+    import paper_2510_24380_amd as apex
+    lib_h, dec_h, (lib, dec, eng), sample = probe12m
+    quant = lambda h, p: float(np.quantile(sample[:, h], p))  # noqa: E731
+    buf = apex.ResultBuffers(1_000_000, dec.n_heads)
+    for k, target in ((100_000, 1), (1_000_000, 2)):
+        q = g.probe_query(12, quant, k, target=target)
+        print(f"case: probe 12M pinned result buffers k={k}", flush=True)
+        r_ref = eng.search(q)
+        r_buf = eng.search(q, out=buf)
+        assert np.shares_memory(r_buf.ids, buf.ids)
+        _same_result(r_buf, r_ref, f"pinned buffers k={k}")
+
+
 @pytest.fixture(scope="module")
 def mlp1m():
     lib_h = g.make_library(13, [2, 3, 2], [900, 800, 30, 40, 50, 310, 1000], 64)
@@ -83,6 +107,18 @@ def test_mlp_long_answer_fp32(mlp1m):
     print(f"case: mlp {lib_h.n_compounds} compounds fp32 k=1e5", flush=True)
     r = eng.search(q, precision="fp32")
     check_fp32_exact(lib_h, dec_h, q, r, "mlp fp32 k=1e5")
+
+
+def test_mlp_pinned_result_buffers(mlp1m):
+    """The MLP engine's answer heads have a 16-float row stride on the device and
+    5 heads per row in the result: the pitched copy into pinned arrays equals
+    the ordinary readback."""
+    import paper_2510_24380_amd as apex
+    lib_h, dec_h, (lib, dec, eng), sample = mlp1m
+    q = _mlp_query(sample, 100_000)
+    print("case: mlp pinned result buffers fp32 k=1e5", flush=True)
+    buf = apex.ResultBuffers(100_000, dec.n_heads)
+    _same_result(eng.search(q, precision="fp32", out=buf), eng.search(q, precision="fp32"), "mlp pinned buffers")
 
 
 def test_mlp_long_answer_bf16(mlp1m):
