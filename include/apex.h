@@ -195,6 +195,11 @@ typedef struct {
  * (linear-probe) engines only; APEX_E_UNSUPPORTED elsewhere. */
 #define APEX_QUERY_KEEP_VIOLATORS 1u
 
+/* Result arrays are the caller's host memory. Short answers are copied in from
+ * the library's readback buffer; answers whose arrays exceed 4 MB are copied
+ * from the device straight into them (n_found entries each), which is a DMA
+ * when they are pinned host memory (hipHostMalloc): a caller that reuses
+ * pinned result arrays across searches pays no host copy for them. */
 typedef struct {
   uint64_t capacity;    /* entries each array below can hold (>= k) */
   uint64_t* ids;        /* host [capacity] compound ids, best first */
