@@ -133,6 +133,41 @@ def valu_estimate(prec, flops_per_compound, compounds_per_launch, avg_launch_ms)
             "measured_clock_ghz": clock}
 
 
+def reference_gemm(precs, n=8192, iters=40):
+    """Dense square GEMM rate of the vendor library (hipBLASLt through torch) on this
+    GPU, in TFLOP/s per precision: a measured ceiling for MFMA work under the same
+    clock and power limits, reported beside the published peak."""
+    import torch
+    dev = torch.device("cuda:0")
+    out = {}
+    for p in precs:
+        if p == "fp8":
+            a = torch.randn(n, n, device=dev).to(torch.float8_e4m3fn)
+            b = torch.randn(n, n, device=dev).to(torch.float8_e4m3fn).t()
+            one = torch.tensor(1.0, device=dev)
+            f = lambda: torch._scaled_mm(a, b, scale_a=one, scale_b=one, out_dtype=torch.bfloat16)
+        else:
+            dt = torch.bfloat16 if p == "bf16" else torch.float32
+            a = torch.randn(n, n, device=dev, dtype=dt)
+            b = torch.randn(n, n, device=dev, dtype=dt)
+            f = lambda: torch.matmul(a, b)
+        its = iters if p != "fp32" else max(4, iters // 8)
+        for _ in range(3):
+            f()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(its):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        tf = 2.0 * n ** 3 * its / (e0.elapsed_time(e1) * 1e-3) / 1e12
+        out[p] = {"tflops": tf, "frac_of_peak": tf * 1e12 / PEAK[p]}
+        del a, b, f
+    torch.cuda.empty_cache()
+    return out
+
+
 def algorithmic_flops_per_compound(dims):
     """MFMA-class FLOPs per compound once the first layer is hoisted into the
     per-synthon tables: 2 * sum over the remaining layers of in * out."""
@@ -691,6 +726,15 @@ def main():
         out["p99_latency_ms_c1_stream"] = out["serving"]["served"]["p99_latency_ms"]
     del eng
     torch.cuda.empty_cache()
+    if not args.quick:
+        ref = reference_gemm(("bf16", "fp8", "fp32"))
+        out["reference_gemm"] = {"shape": "8192 x 8192 x 8192", "library": "hipBLASLt (torch.matmul; FP8: "
+                                 "torch._scaled_mm, E4M3 operands, BF16 output)", **ref}
+        roof["reference_gemm_tflops"] = ref[args.precision]["tflops"]
+        roof["frac_of_reference_gemm"] = roof["achieved"] / ref[args.precision]["tflops"]
+        for p, o in others.items():
+            o["frac_of_reference_gemm"] = o["roofline_frac"] * PEAK[p] / 1e12 / ref[p]["tflops"]
+        log("reference GEMM: " + ", ".join(f"{p} {v['tflops']:.0f} TFLOP/s" for p, v in ref.items()))
     if "c3" in legs:
         c3, c4 = c3_leg(serve_queries=60 if "c4" in legs else 0)
         out["c3"] = c3

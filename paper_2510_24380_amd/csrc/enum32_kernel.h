@@ -48,9 +48,10 @@ template <> struct Mfma32<APEX_PREC_FP8> {
   static constexpr int KS = 64, E = 32, EB = 1;
   using frag = i32x8;
   __device__ static inline frag frag_at(const unsigned char* base, int s, int lane) {
-    const int4 lo = *reinterpret_cast<const int4*>(base + (size_t)s * 2048 + lane * 16);
-    const int4 hi = *reinterpret_cast<const int4*>(base + (size_t)s * 2048 + 1024 + lane * 16);
-    return frag{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i32x4;
+    const i32x4 lo = *reinterpret_cast<const i32x4*>(base + (size_t)(s * 128 + lane) * 16);
+    const i32x4 hi = *reinterpret_cast<const i32x4*>(base + (size_t)(s * 128 + 64 + lane) * 16);
+    return frag{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
   }
   __device__ static inline f32x16 mma(frag a, frag b, f32x16 c, int sa) {
     // E4M3 x E4M3 (format selectors 0); E8M0 scales sa on A, 127 (one) on B
