@@ -72,6 +72,10 @@ def build(verbose: bool = False) -> str:
     probe_src = os.path.join(HERE, "probe", "mfma_probe.hip")
     probe_so = os.path.join(HERE, "probe", "libmfma_probe.so")
     subprocess.check_call(["hipcc"] + FLAGS + ["-shared", probe_src, "-o", probe_so])
+    # issue-rate probe: accumulators in VGPRs, as the fused kernels keep them
+    issue_src = os.path.join(HERE, "probe", "issue_probe.hip")
+    issue_so = os.path.join(HERE, "probe", "libissue_probe.so")
+    subprocess.check_call(["hipcc"] + FLAGS + ["-mllvm", "-amdgpu-mfma-vgpr-form=1", "-shared", issue_src, "-o", issue_so])
     if verbose:
         print("built", SO, "and", probe_so)
     return SO
