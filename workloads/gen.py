@@ -480,9 +480,10 @@ def serving_stream(seed: int, n: int, qps: float, reaction_counts: Sequence[int]
     objective weights N(0, 1) over the heads, 2-6 one-sided bounds on distinct
     heads at quantiles drawn from [0.6, 0.9] (values from `head_quantile(head, q)`,
     which the caller supplies), k drawn from `ks`, and a library that is a subset
-    of reactions whose compound count is drawn log-uniformly in [size_lo, size_hi]
-    (reactions added in a seeded random order until the target is reached).
-    Returns a list of (arrival_s, Query)."""
+    of whole reactions: a target count is drawn log-uniformly in [size_lo, size_hi],
+    and reactions are added in a seeded random order until the target is reached,
+    skipping any that would take the subset past size_hi (so one large reaction
+    cannot carry it out of the range). Returns a list of (arrival_s, Query)."""
     u = uniform_f64(seed, "serve_u", 16 * n).reshape(n, 16)
     z = normal_f64(seed, "serve_w", n * n_heads).reshape(n, n_heads)
     gaps = -_log(1.0 - uniform_f64(seed, "serve_gap", n)) / qps
@@ -494,10 +495,15 @@ def serving_stream(seed: int, n: int, qps: float, reaction_counts: Sequence[int]
         target = math.exp(math.log(size_lo) + (math.log(size_hi) - math.log(size_lo)) * float(u[i, 0]))
         subset, tot = [], 0
         for r in order:
+            c = int(reaction_counts[int(r)])
+            if tot + c > size_hi:
+                continue
             subset.append(int(r))
-            tot += int(reaction_counts[int(r)])
+            tot += c
             if tot >= target:
                 break
+        if not subset:  # every reaction is larger than size_hi: the smallest one
+            subset = [int(np.argmin(np.asarray(reaction_counts)))]
         n_thr = 2 + int(u[i, 1] * 5)
         heads = np.argsort(uniform_f64(seed + 7919 * (i + 1), "serve_heads", n_heads), kind="stable")[:n_thr]
         cons = []
