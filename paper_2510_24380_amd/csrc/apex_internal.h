@@ -155,6 +155,10 @@ struct EnumArgs {
   uint64_t n_reactions;
   uint64_t n_total;        // compounds in the library
   float* heads_out;        // [n_ids][16]
+  // tile mode of the 32x32 kernels: eight region counters and an exit counter,
+  // zero when a launch starts (the launch leaves them zero); null for static
+  // work ranges
+  uint32_t* work;
 };
 
 }  // namespace apex

@@ -61,6 +61,7 @@ template <> struct Mfma32<APEX_PREC_FP8> {
 constexpr int kE8M0One = 127;
 
 constexpr int kTileA32 = 8;  // A-rows per tile (2 per wave)
+constexpr int kWorkRun = 2;  // tiles a workgroup takes at a time (dynamic work)
 // Word 3 of a raw buffer resource on gfx9-family parts (32-bit data format;
 // untyped loads use only the range and base).
 constexpr int kBufferWord3 = 0x00020000;
@@ -118,7 +119,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // the GEMM's power-of-two scale S2 as an E8M0 exponent (127 + log2 S2)
   const int s2e = (int)((__float_as_uint(A.pd.scal[0]) >> 23) & 0xffu);
 
-  // Work range (XCD-aware contiguous runs, as in the 16x16 kernel).
+  // Work range. Static: XCD-aware contiguous runs, as in the 16x16 kernel.
+  // Dynamic (tile mode with work counters): the launch's tiles form eight
+  // contiguous regions, one per XCD (workgroups are dealt to the XCDs in turn);
+  // a workgroup takes kWorkRun tiles at a time from its own XCD's region, then
+  // from the others once that one is used up. XCDs and CUs run at different
+  // clocks, and equal static shares left the faster ones idle at the end of a
+  // launch.
+  const bool dyn = !GATHER && A.work != nullptr;
   uint64_t v, vend;
   {
     const uint32_t G = gridDim.x, bid = blockIdx.x;
@@ -129,6 +137,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       v = (uint64_t)wg * per_wg;
       vend = v + per_wg;
       if (v >= A.n_ids) return;
+    } else if (dyn) {
+      v = vend = 0;  // set by the first take below
     } else {
       const uint64_t n = A.tile_end - A.tile_begin;
       const uint64_t per = (n + G - 1) / G;
@@ -137,6 +147,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       if (v >= vend) return;
     }
   }
+  // the run just taken, and (slot 2) how many regions were found used up
+  __shared__ uint64_t s_run[3];
+  if (dyn && tid == 0) s_run[2] = 0;
+  auto uniform64 = [](uint64_t x) {  // a workgroup-uniform value into scalar registers
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+  };
+  // Takes the workgroup's next run into [v, vend); v == vend when no tile is left.
+  auto take_run = [&]() {
+    if (tid == 0) {
+      const uint64_t n = A.tile_end - A.tile_begin, reg = (n + 7) / 8;
+      const uint32_t home = blockIdx.x % 8;
+      uint64_t r0 = 0, r1 = 0, tried = s_run[2];
+      for (; tried < 8; ++tried) {
+        const uint32_t r = (home + (uint32_t)tried) % 8;
+        const uint64_t rb = r * reg, re = rb + reg < n ? rb + reg : n;
+        if (rb >= re) continue;
+        const uint64_t o = rb + atomicAdd(&A.work[r], (uint32_t)kWorkRun);
+        if (o < re) {
+          r0 = A.tile_begin + o;
+          r1 = A.tile_begin + (o + kWorkRun < re ? o + kWorkRun : re);
+          break;
+        }
+      }
+      s_run[0] = r0;
+      s_run[1] = r1;
+      s_run[2] = tried;
+    }
+    __syncthreads();
+    v = uniform64(s_run[0]);
+    vend = uniform64(s_run[1]);
+  };
 
   // Resident LDS: GEMM start values, or the one-hidden-layer output weights.
   {
@@ -183,23 +225,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __syncthreads();
   };
 
+  if (dyn) take_run();
   uint32_t si = 0;
   SelDev S{};
   ReactDev Rt{};
   uint64_t s_end = 0;
-  if (!GATHER) {
+  if (!GATHER && v < vend) {
     si = find_sel(A.sel, A.n_sel, v);
     S = A.sel[si];
     Rt = A.react[S.t];
     s_end = S.tile_start + (uint64_t)((Rt.nA + TA - 1) / TA) * S.tiles_b;
   }
 
-  for (; v < vend; v += (GATHER ? vend : 1)) {
+  for (; v < vend || (dyn && (take_run(), v < vend)); v += (GATHER ? vend : 1)) {
     // ---------------- locate the tile and stage its rows ----------------
     uint32_t a0 = 0, b0 = 0;
     if (!GATHER) {
-      while (v >= s_end) {
-        ++si;
+      // the tile's selection entry: the next ones in turn, or (a run taken
+      // elsewhere in the launch) a binary search
+      for (int hop = 0; v < S.tile_start || v >= s_end; ++hop) {
+        si = (dyn && (hop == 2 || v < S.tile_start)) ? find_sel(A.sel, A.n_sel, v) : si + 1;
         S = A.sel[si];
         Rt = A.react[S.t];
         s_end = S.tile_start + (uint64_t)((Rt.nA + TA - 1) / TA) * S.tiles_b;
@@ -532,6 +577,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
     if (NL != 2 && !GATHER) __syncthreads();  // staged rows are reused by the next tile
+  }
+  // Dynamic work: the last workgroup to finish (every other one has taken its
+  // last run) leaves the counters at zero for the next launch on this stream.
+  if (dyn && tid == 0 && atomicAdd(&A.work[8], 1u) == gridDim.x - 1) {
+    for (int r = 0; r < 9; ++r) atomicExch(&A.work[r], 0u);
   }
 }
 

@@ -379,7 +379,7 @@ uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev
 }
 
 apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t v0, uint64_t v1,
-                      const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, hipStream_t s) {
+                      const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, uint32_t* work, hipStream_t s) {
   // the tile kernels keep every fused query's parameters in LDS
   if (nq == 0 || nq > APEX_MAX_FUSED_QUERIES) return set_error(APEX_E_INVALID, "internal: %u fused queries", nq);
   const PrecState& PS = E->prec[prec];
@@ -396,6 +396,7 @@ apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t
   a.n_total = E->lib->total;
   a.tile_begin = v0;
   a.tile_end = v1;
+  a.work = work;
   uint32_t grid_full = (uint32_t)(E->n_cu * PS.wg_per_cu);
   grid_full = std::max<uint32_t>(8, grid_full / 8 * 8);
   const uint64_t nt = v1 - v0;
@@ -590,6 +591,7 @@ struct Shared {
   float* sample_heads = nullptr;
   uint32_t n_sample = 0;
   uint32_t n_flags = 0;
+  uint32_t* work = nullptr;  // tile-sharing counters of the fused passes
 };
 
 uint32_t sample_count(const apex_engine* E, const std::vector<QPlan>& P) {
@@ -620,6 +622,7 @@ void batch_layout(const apex_engine* E, const apex_query* qs, uint32_t n, Bump& 
   sh.sample_ids = b.take<uint64_t>(sh.n_sample);
   // the linear path scores its sample from the query tables, without heads
   sh.sample_heads = b.take<float>(E->scalar ? 1 : (size_t)sh.n_sample * kHeadsPad);
+  sh.work = b.take<uint32_t>(kWorkCounters);
   for (uint32_t i = 0; i < n; ++i) query_layout(T, sh.n_flags, b, P[i]);
   for (uint32_t i = 0; i < n; ++i) out_layout(b, P[i]);  // adjacent readback blocks
 }
@@ -678,6 +681,10 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   }
   HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(sh.qx, qx.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
+  {
+    const apex_status st = fill_u32(sh.work, kWorkCounters, 0u, s);  // the passes leave them zero
+    if (st != APEX_OK) return st;
+  }
   if (!plan.empty())
     HIP_TRY(hipMemcpyAsync(sh.plan, plan.data(), sizeof(SelDev) * plan.size(), hipMemcpyHostToDevice, s));
 
@@ -714,7 +721,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
   const uint32_t last_flag = sh.n_flags - 1;  // flag slot of the closing selections (never set)
   for (size_t c = 0; c < chunks.size(); ++c) {
     apex_status st = enum_pass(E, prec, sh.plan, (uint32_t)plan.size(), chunks[c].first, chunks[c].second, sh.qd,
-                               nq, plan_compounds(E, prec, plan, chunks[c].first, chunks[c].second), s);
+                               nq, plan_compounds(E, prec, plan, chunks[c].first, chunks[c].second), sh.work, s);
     if (st != APEX_OK) return st;
     HIP_TRY(launch_select(sh.qd, nq, (uint32_t)c, 0, s));
   }
@@ -787,7 +794,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
       for (size_t c = 0; c < chunks.size(); ++c) {
         const uint64_t cc = plan_compounds(E, prec, plan, chunks[c].first, chunks[c].second);
         apex_status st = enum_pass(E, prec, sh.plan, (uint32_t)plan.size(), chunks[c].first, chunks[c].second,
-                                   sh.qd, nq, cc, s);
+                                   sh.qd, nq, cc, sh.work, s);
         if (st != APEX_OK) return st;
         HIP_TRY(launch_select(sh.qd, nq, (uint32_t)c, 0, s));
         scored += cc;
@@ -804,7 +811,7 @@ static apex_status run_search(apex_engine* E, const apex_query* qs, uint32_t nq,
       HIP_TRY(hipMemcpyAsync(sh.qd, qd.data(), sizeof(QueryDev) * nq, hipMemcpyHostToDevice, s));
       const uint64_t cc = plan_compounds(E, prec, plan, chunks[c].first, chunks[c].second);
       apex_status st = enum_pass(E, prec, sh.plan, (uint32_t)plan.size(), chunks[c].first, chunks[c].second,
-                                 sh.qd, nq, cc, s);
+                                 sh.qd, nq, cc, sh.work, s);
       if (st != APEX_OK) return st;
       HIP_TRY(launch_select(sh.qd, nq, (uint32_t)c, 0, s));
       scored += cc;

@@ -75,8 +75,12 @@ std::vector<uint32_t> subset_bits(const apex_engine* E, const apex_query* q);
 apex_status query_device_init(const apex_engine* E, const apex_query* q, const QPlan& P, hipStream_t s);
 apex_status fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 // One pass of the fused kernel over tiles [v0, v1) of a tile plan (async).
+// work: kWorkCounters counters in device memory, zero before the first pass on
+// the stream (each pass leaves them zero); the BF16/FP8 tile kernels share out
+// their tiles through them.
+constexpr uint32_t kWorkCounters = 9;
 apex_status enum_pass(apex_engine* E, int prec, const SelDev* plan_dev, uint32_t n_sel, uint64_t v0, uint64_t v1,
-                      const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, hipStream_t s);
+                      const QueryDev* qd_dev, uint32_t nq, uint64_t compounds, uint32_t* work, hipStream_t s);
 // Compounds of a host tile plan inside tiles [v0, v1).
 uint64_t plan_compounds(const apex_engine* E, int prec, const std::vector<SelDev>& plan, uint64_t v0, uint64_t v1);
 // Threshold warm start from a sample of compounds of a tile plan (n_tiles tiles,

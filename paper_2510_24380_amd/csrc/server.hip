@@ -130,6 +130,7 @@ struct apex_server {
   QueryDev* qd_dev = nullptr;
   QueryDev* qx_dev = nullptr;
   SelDev* plan_dev = nullptr;
+  uint32_t* work = nullptr;  // tile-sharing counters of the fused passes
   uint64_t* sample_ids = nullptr;
   float* sample_heads = nullptr;
   uint32_t n_sample = 0;
@@ -204,7 +205,7 @@ apex_status run_pass(apex_server* S, int prec, uint32_t c, const std::vector<SQ*
   if (v0 > 0 || v1 < n_tiles) n_comp = plan_compounds(S->E, prec, plan, v0, v1);
   const double t0 = now_s();
   st = enum_pass(S->E, prec, S->plan_dev, (uint32_t)plan.size(), v0, v1, S->qd_dev, (uint32_t)S->qd.size(), n_comp,
-                 S->s);
+                 S->work, S->s);
   if (st != APEX_OK) return st;
   e = launch_select(S->qd_dev, (uint32_t)S->qd.size(), c, 0, S->s);
   if (e == hipSuccess) e = hipStreamSynchronize(S->s);
@@ -520,6 +521,7 @@ extern "C" apex_status apex_server_create(apex_engine* eng, const apex_server_co
   S->qd_dev = b.take<QueryDev>(cfg->max_active);
   S->qx_dev = b.take<QueryDev>(cfg->max_active);
   S->plan_dev = b.take<SelDev>(L->T);
+  S->work = b.take<uint32_t>(kWorkCounters);
   S->sample_ids = b.take<uint64_t>(S->n_sample);
   S->sample_heads = b.take<float>((size_t)S->n_sample * kHeadsPad);
   if (b.off >= cfg->pool_bytes)
@@ -532,6 +534,7 @@ extern "C" apex_status apex_server_create(apex_engine* eng, const apex_server_co
   hipError_t e = hipMemcpyAsync(S->qd_dev, S->qd.data(), sizeof(QueryDev) * cfg->max_active, hipMemcpyHostToDevice, S->s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(S->qx_dev, S->qx.data(), sizeof(QueryDev) * cfg->max_active, hipMemcpyHostToDevice, S->s);
+  if (e == hipSuccess && fill_u32(S->work, kWorkCounters, 0u, S->s) != APEX_OK) e = hipErrorLaunchFailure;
   if (e == hipSuccess) e = hipStreamSynchronize(S->s);
   if (e != hipSuccess) return set_error(APEX_E_DEVICE, "server setup: %s", hipGetErrorString(e));
   int dev = 0;
