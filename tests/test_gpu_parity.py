@@ -92,6 +92,49 @@ def test_mixed_subset_and_k_beyond_feasible(mixed):
     assert ref.n_feasible < 5000 and len(r.ids) == ref.n_feasible
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_low_precision_k_beyond_feasible(mixed, prec):
+    """k above the number of feasible compounds, in the precisions whose tile
+    passes share their tiles out between workgroups at run time: the answer is
+    the feasible set, each compound once (no tile skipped or scored twice), and
+    many small launches give the same bits as the default ones."""
+    from parity import _feasible64, library_scales
+    lib_h, dec_h, (lib, dec, eng), sample = mixed
+    print(f"case: mixed subset, k beyond feasible, {prec}", flush=True)
+    q = mixed_query(sample, 5000, reactions=[1, 3])
+    r32 = eng.search(q, precision="fp32")
+    ref = check_fp32_exact(lib_h, dec_h, q, r32, "fp32 reference")
+    assert ref.n_feasible < 5000
+    hs, _ = library_scales(lib_h, dec_h, q)
+    runs = []
+    for chunk in (None, "2048"):
+        if chunk:
+            os.environ["APEX_TEST_CHUNK"] = chunk
+        try:
+            r = eng.search(q, precision=prec)
+        finally:
+            os.environ.pop("APEX_TEST_CHUNK", None)
+        ids = r.ids.tolist()
+        assert len(set(ids)) == len(ids), f"{prec}: a compound returned twice"
+        got, want = set(ids), set(r32.ids.tolist())
+        # the answer is rescored in FP32 against the exact bounds
+        extra = np.array(sorted(got - want), np.uint64)
+        if len(extra):
+            h64 = oracle.heads(lib_h, dec_h, extra)
+            assert np.all(_feasible64(h64, q, slack=2e-5 * float(np.max(hs)))), f"{prec}: infeasible compound"
+        # a feasible compound may be missed only within the low-precision error of a bound
+        missing = np.array(sorted(want - got), np.uint64)
+        if len(missing):
+            h64 = oracle.heads(lib_h, dec_h, missing)
+            near = ~_feasible64(h64, q, slack=-0.05 * float(np.max(hs)))
+            assert np.all(near), f"{prec}: {int(np.sum(~near))} feasible compounds missed away from the bounds"
+        print(f"[{prec} chunk={chunk}] {len(ids)} returned of {ref.n_feasible} feasible; "
+              f"{len(missing)} missed at a bound, {len(extra)} extra at a bound", flush=True)
+        runs.append(r)
+    assert np.array_equal(runs[0].ids, runs[1].ids)
+    assert np.array_equal(runs[0].objective.view(np.uint32), runs[1].objective.view(np.uint32))
+
+
 def test_all_infeasible_returns_nothing(mixed):
     lib_h, dec_h, (lib, dec, eng), sample = mixed
     print("case: all infeasible", flush=True)
