@@ -61,7 +61,6 @@ template <> struct Mfma32<APEX_PREC_FP8> {
 constexpr int kE8M0One = 127;
 
 constexpr int kTileA32 = 8;  // A-rows per tile (2 per wave)
-constexpr int kWorkRun = 2;  // tiles a workgroup takes at a time (dynamic work)
 // Word 3 of a raw buffer resource on gfx9-family parts (32-bit data format;
 // untyped loads use only the range and base).
 constexpr int kBufferWord3 = 0x00020000;
@@ -119,13 +118,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // the GEMM's power-of-two scale S2 as an E8M0 exponent (127 + log2 S2)
   const int s2e = (int)((__float_as_uint(A.pd.scal[0]) >> 23) & 0xffu);
 
-  // Work range. Static: XCD-aware contiguous runs, as in the 16x16 kernel.
-  // Dynamic (tile mode with work counters): the launch's tiles form eight
-  // contiguous regions, one per XCD (workgroups are dealt to the XCDs in turn);
-  // a workgroup takes kWorkRun tiles at a time from its own XCD's region, then
-  // from the others once that one is used up. XCDs and CUs run at different
-  // clocks, and equal static shares left the faster ones idle at the end of a
-  // launch.
+  // Work range: XCD-aware contiguous runs, or (tile mode with work counters)
+  // runs taken at run time (take_tile_run).
   const bool dyn = !GATHER && A.work != nullptr;
   uint64_t v, vend;
   {
@@ -147,38 +141,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       if (v >= vend) return;
     }
   }
-  // the run just taken, and (slot 2) how many regions were found used up
-  __shared__ uint64_t s_run[3];
+  __shared__ uint64_t s_run[3];  // dynamic work: the run taken, regions used up
   if (dyn && tid == 0) s_run[2] = 0;
-  auto uniform64 = [](uint64_t x) {  // a workgroup-uniform value into scalar registers
-    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
-           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
-  };
-  // Takes the workgroup's next run into [v, vend); v == vend when no tile is left.
-  auto take_run = [&]() {
-    if (tid == 0) {
-      const uint64_t n = A.tile_end - A.tile_begin, reg = (n + 7) / 8;
-      const uint32_t home = blockIdx.x % 8;
-      uint64_t r0 = 0, r1 = 0, tried = s_run[2];
-      for (; tried < 8; ++tried) {
-        const uint32_t r = (home + (uint32_t)tried) % 8;
-        const uint64_t rb = r * reg, re = rb + reg < n ? rb + reg : n;
-        if (rb >= re) continue;
-        const uint64_t o = rb + atomicAdd(&A.work[r], (uint32_t)kWorkRun);
-        if (o < re) {
-          r0 = A.tile_begin + o;
-          r1 = A.tile_begin + (o + kWorkRun < re ? o + kWorkRun : re);
-          break;
-        }
-      }
-      s_run[0] = r0;
-      s_run[1] = r1;
-      s_run[2] = tried;
-    }
-    __syncthreads();
-    v = uniform64(s_run[0]);
-    vend = uniform64(s_run[1]);
-  };
+  auto take_run = [&]() { take_tile_run(A, s_run, v, vend); };
 
   // Resident LDS: GEMM start values, or the one-hidden-layer output weights.
   {
@@ -578,11 +543,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
     if (NL != 2 && !GATHER) __syncthreads();  // staged rows are reused by the next tile
   }
-  // Dynamic work: the last workgroup to finish (every other one has taken its
-  // last run) leaves the counters at zero for the next launch on this stream.
-  if (dyn && tid == 0 && atomicAdd(&A.work[8], 1u) == gridDim.x - 1) {
-    for (int r = 0; r < 9; ++r) atomicExch(&A.work[r], 0u);
-  }
+  if (dyn) release_tile_counters(A);
 }
 
 }  // namespace apex

@@ -142,4 +142,55 @@ __device__ __forceinline__ uint32_t find_sel(const SelDev* sel, uint32_t n, uint
   return lo;
 }
 
+// Dynamic tile sharing of the tile kernels (tile mode with work counters). A
+// launch's tiles form eight contiguous regions, one per XCD (workgroups are
+// dealt to the XCDs in turn); a workgroup takes kWorkRun tiles at a time from
+// its own XCD's region through that region's counter, then from the others once
+// that one is used up. XCDs and CUs run at different clocks, and equal static
+// shares left the faster ones idle at the end of a launch.
+constexpr int kWorkRun = 2;
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {  // workgroup-uniform value into scalar registers
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+
+// Every thread of the workgroup calls it (it holds a barrier). Thread 0 takes
+// the next run into s_run[0..1]; s_run[2] counts the regions found used up
+// (zero before the first call). Returns the run as [v, vend), empty when no
+// tile is left.
+__device__ __forceinline__ void take_tile_run(const EnumArgs& A, uint64_t* s_run, uint64_t& v, uint64_t& vend) {
+  if (threadIdx.x == 0) {
+    const uint64_t n = A.tile_end - A.tile_begin, reg = (n + 7) / 8;
+    const uint32_t home = blockIdx.x % 8;
+    uint64_t r0 = 0, r1 = 0, tried = s_run[2];
+    for (; tried < 8; ++tried) {
+      const uint32_t r = (home + (uint32_t)tried) % 8;
+      const uint64_t rb = r * reg, re = rb + reg < n ? rb + reg : n;
+      if (rb >= re) continue;
+      const uint64_t o = rb + atomicAdd(&A.work[r], (uint32_t)kWorkRun);
+      if (o < re) {
+        r0 = A.tile_begin + o;
+        r1 = A.tile_begin + (o + kWorkRun < re ? o + kWorkRun : re);
+        break;
+      }
+    }
+    s_run[0] = r0;
+    s_run[1] = r1;
+    s_run[2] = tried;
+  }
+  __syncthreads();
+  v = uniform64(s_run[0]);
+  vend = uniform64(s_run[1]);
+}
+
+// Once per workgroup, after its last run: the last workgroup to finish (every
+// other one has taken its last run) leaves the counters at zero for the next
+// launch on the stream.
+__device__ __forceinline__ void release_tile_counters(const EnumArgs& A) {
+  if (threadIdx.x == 0 && atomicAdd(&A.work[8], 1u) == gridDim.x - 1) {
+    for (int r = 0; r < 9; ++r) atomicExch(&A.work[r], 0u);
+  }
+}
+
 }  // namespace apex

@@ -80,7 +80,10 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
 
   // Work range of this workgroup. Tiles (or gathered compounds) are split into
   // contiguous runs; consecutive runs go to workgroups on the same XCD (blocks
-  // are dispatched to XCDs round robin), so neighbouring tiles share that XCD's L2.
+  // are dispatched to XCDs round robin), so neighbouring tiles share that XCD's
+  // L2. With work counters (tile mode), runs are taken at run time instead
+  // (take_tile_run).
+  const bool dyn = !GATHER && A.work != nullptr;
   uint64_t v, vend;
   {
     const uint32_t G = gridDim.x, bid = blockIdx.x;
@@ -91,6 +94,8 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
       v = (uint64_t)wg * per_wg;
       vend = v + per_wg;
       if (v >= A.n_ids) return;
+    } else if (dyn) {
+      v = vend = 0;  // set by the first take below
     } else {
       const uint64_t n = A.tile_end - A.tile_begin;
       const uint64_t per = (n + G - 1) / G;
@@ -123,18 +128,21 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
   };
   auto pre_get = [](const PreV& p, int q) { return make_uint4(p[4 * q], p[4 * q + 1], p[4 * q + 2], p[4 * q + 3]); };
 
+  __shared__ uint64_t s_run[3];  // dynamic work: the run taken, regions used up
+  if (dyn && tid == 0) s_run[2] = 0;
+  if (dyn) take_tile_run(A, s_run, v, vend);
   uint32_t si = 0;
   SelDev S{};
   ReactDev Rt{};
   uint64_t s_end = 0;
-  if (!GATHER) {
+  if (!GATHER && v < vend) {
     si = find_sel(A.sel, A.n_sel, v);
     S = A.sel[si];
     Rt = A.react[S.t];
     s_end = S.tile_start + (uint64_t)((Rt.nA + TA - 1) / TA) * S.tiles_b;
   }
 
-  for (; v < vend; v += (GATHER ? vend : 1)) {
+  for (; v < vend || (dyn && (take_tile_run(A, s_run, v, vend), v < vend)); v += (GATHER ? vend : 1)) {
     PreV pre;
     // first GEMM weight chunk: loads issued now, stored after the activation phase
     if (NL == 2) {
@@ -147,8 +155,10 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
     // ---------------- locate the tile and stage its rows ----------------
     uint32_t a0 = 0, b0 = 0;
     if (!GATHER) {
-      while (v >= s_end) {
-        ++si;
+      // the tile's selection entry: the next ones in turn, or (a run taken
+      // elsewhere in the launch) a binary search
+      for (int hop = 0; v < S.tile_start || v >= s_end; ++hop) {
+        si = (dyn && (hop == 2 || v < S.tile_start)) ? find_sel(A.sel, A.n_sel, v) : si + 1;
         S = A.sel[si];
         Rt = A.react[S.t];
         s_end = S.tile_start + (uint64_t)((Rt.nA + TA - 1) / TA) * S.tiles_b;
@@ -362,6 +372,7 @@ __global__ __launch_bounds__(kWaves16 * 64) __attribute__((amdgpu_waves_per_eu(2
     }
     if (NL != 2 && !GATHER) __syncthreads();  // staged rows are reused by the next tile
   }
+  if (dyn) release_tile_counters(A);
 }
 
 // Heads of listed compounds with a two-hidden-layer decoder, for short lists
