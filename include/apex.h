@@ -264,7 +264,8 @@ typedef struct {
   void* pool;               /* device memory for per-query workspaces */
   size_t pool_bytes;        /* admission budget: queries wait until their workspace fits */
   uint32_t max_active;      /* queries enumerating at once, <= APEX_MAX_FUSED_QUERIES */
-  void* stream;             /* hipStream_t the server launches on */
+  void* stream;             /* hipStream_t the server launches on (one: each pass already fuses
+                               every active query, and passes depend on each other's thresholds) */
   uint64_t chunk_compounds; /* scheduling granularity; 0 = engine default */
 } apex_server_config;
 
@@ -288,6 +289,8 @@ apex_status apex_server_create(apex_engine* eng, const apex_server_config* cfg, 
 apex_status apex_server_submit(apex_server* srv, const apex_query* q, uint64_t* ticket);
 apex_status apex_server_poll(apex_server* srv, uint64_t ticket, apex_result* result, int timeout_ms);
 apex_status apex_server_cancel(apex_server* srv, uint64_t ticket);
+/* Statistics so far (the _get suffix: in C a function cannot take the name of
+ * the struct type apex_server_stats). */
 apex_status apex_server_stats_get(apex_server* srv, apex_server_stats* out);
 apex_status apex_server_destroy(apex_server* srv);
 
